@@ -1,0 +1,160 @@
+#!/usr/bin/env python3
+"""Benchmark of the certified-split lexer on one MI355X.
+
+A step is one scan of the whole hot path -- plan (certificate bitmap + cuts), count walk,
+scan, emit walk -- over the 512 MiB C-like corpus in exact mode (token set C-like-L, lane
+sub-chunks inside 64 KiB chunks), with the input already resident in HBM.  Prints one JSON
+line: whole-job input GB/s, the roofline of the dominant kernel (HIP events around each
+phase, on the scan's stream) and the oracle's single-core rate on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=512 << 20, help="corpus bytes")
+    ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--lane-bytes", type=int, default=0)
+    ap.add_argument("--chunk-bytes", type=int, default=64 << 10)
+    ap.add_argument("--path", type=int, default=0, help="0 default, 1 pipeline, 2 fused")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle CPU time")
+    ap.add_argument("--quiet", action="store_true")
+    return ap.parse_args()
+
+
+def log(args, *a):
+    if not args.quiet:
+        print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import workloads
+    from workloads import tokensets as T
+    import paper_2608_03473_amd as P
+    from paper_2608_03473_amd.hipevents import PhaseEvents
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    n = args.n
+    t0 = time.time()
+    host = workloads.clike(n, args.seed)
+    log(args, f"corpus: {n} bytes in {time.time() - t0:.1f}s")
+    data = torch.from_numpy(host).to(dev)
+    lx = P.Lexer.compile(T.as_tuples(T.CLIKE_L))
+    mode = P.LEX_MODE_EXACT
+    opts = P.RunOpts(chunk_bytes=args.chunk_bytes, lane_bytes=args.lane_bytes, path=args.path)
+    cap = n
+    kinds = torch.empty(cap, dtype=torch.uint8, device=dev)
+    lens = torch.empty(cap, dtype=torch.int32, device=dev)
+    res = torch.zeros(3, dtype=torch.int64, device=dev)
+    ws = torch.empty(lx.workspace_size(n, mode, opts), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        lx.run_into(data, n, mode, kinds, lens, None, cap, res, ws, opts)
+    torch.cuda.synchronize()
+    evs = [PhaseEvents() for _ in range(args.steps)]
+    step_opts = []
+    for e in evs:
+        o = P.RunOpts(chunk_bytes=args.chunk_bytes, lane_bytes=args.lane_bytes, path=args.path)
+        o.events = e.array
+        step_opts.append(o)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        lx.run_into(data, n, mode, kinds, lens, None, cap, res, ws, step_opts[k], stream)
+    torch.cuda.synchronize()
+    t_end = time.perf_counter()
+    ms = (t_end - t_start) * 1e3 / args.steps
+    r = res.cpu().numpy()
+    ntok, err, status = int(r[0]), int(r[1]), int(np.int32(r[2] & 0xFFFFFFFF))
+    nslices = int((int(r[2]) >> 32) & 0xFFFFFFFF)
+    if status != 0 or err != n:
+        print(f"bench: scan failed status={status} error_offset={err} n={n}", file=sys.stderr)
+        sys.exit(1)
+    phases = np.array([e.elapsed_ms() for e in evs])  # steps x 4
+    ph_mean = phases.mean(axis=0)
+    names = ["plan", "count_walk", "scan", "emit_walk"]
+    algo = {"plan": n + n / 8, "count_walk": n, "scan": 0, "emit_walk": n + 5 * ntok}
+    dom = names[int(np.argmax(ph_mean))]
+    achieved = algo[dom] / (ph_mean[names.index(dom)] * 1e-3) / 1e9
+    gbs = n / (ms * 1e-3) / 1e9
+    path_bytes = n + 5 * ntok
+    out = {
+        "metric": "input GB/s lexed, 512 MiB",
+        "value": round(gbs, 3),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {
+            "workload": f"C-like-L exact mode, {n} B C-like corpus (seed {args.seed}), "
+                        f"{args.chunk_bytes} B chunks",
+            "n_bytes": n, "tokens": ntok, "bytes_per_token": round(n / ntok, 3),
+            "slices": nslices, "lane_bytes": args.lane_bytes or "auto", "path": args.path or "default",
+        },
+        "tokens_per_s": round(ntok / (ms * 1e-3), 1),
+        "path_roofline_frac": round(path_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "phase_ms": {k: round(float(v), 4) for k, v in zip(names, ph_mean)},
+        "roofline": {
+            "bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "algorithmic_bytes_per_launch": int(algo[dom]),
+        },
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(host, args)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(host, args):
+    """The oracle (plain serial NFA lexer, single core) on a bounded prefix of the corpus."""
+    import oracle
+    from workloads import tokensets as T
+
+    oc = oracle.OracleSet(T.as_tuples(T.CLIKE_L))
+    probe = 4 << 20
+    t = time.perf_counter()
+    oc.lex(host[:probe])
+    rate = probe / (time.perf_counter() - t)
+    size = int(min(host.size, max(probe, rate * args.cpu_seconds)))
+    t = time.perf_counter()
+    k, _, con = oc.lex(host[:size])
+    dt = time.perf_counter() - t
+    log(args, f"oracle: {size} bytes, {len(k)} tokens in {dt:.1f}s")
+    return {"value": round(size / dt / 1e9, 5), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {size} bytes of the same corpus ({len(k)} tokens, {dt:.1f} s)"}
+
+
+if __name__ == "__main__":
+    main()

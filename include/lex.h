@@ -1,0 +1,168 @@
+/*
+ * lex.h -- C ABI of the MI355X certified-split lexer (gfx950, HIP).
+ *
+ * What it computes.  A token set is a list of byte regexes with tie-break priorities and
+ * a flag marking the kinds a caller discards (the set I).  lex_compile builds, once, the
+ * longest-match DFA whose accepting map resolves same-length ties by lower priority and
+ * then lower index (Section 3), and its two 256-bit certificate maps: the exact map of
+ * Definition 2 and the modulo-I map of Definition 3, each intersected with the bytes q0
+ * consumes live (the useful sets of Corollary 2 and Proposition 2).  lex_run then scans a
+ * device-resident byte buffer: it cuts the buffer only immediately before certified bytes,
+ * scans every slice independently from q0 with the longest-match loop of Section 3, and
+ * concatenates the per-slice (kind, length) streams in order.  By Theorem 1 (exact mode)
+ * and Theorem 3 (modulo-I mode) the result equals the serial scan of the whole buffer,
+ * after deleting discarded kinds in modulo-I mode.
+ *
+ * Malformed input.  The scan reports con(w), the final committed offset (Section 3), as
+ * error_offset; error_offset == n exactly when the input is completely tokenizable.  The
+ * tokens returned are those the serial scan emits before con(w): the output is truncated
+ * after the first slice that does not consume its whole length (Corollary 1; the same
+ * rule is applied in modulo-I mode, where the paper states no corollary -- see the
+ * reading recorded with the design).
+ *
+ * Conventions
+ *   - All sizes are in bytes unless stated; kinds are u8, lengths u32, offsets u64.
+ *   - "device pointer" = memory of the current HIP device (e.g. a torch CUDA tensor);
+ *     "host pointer" = ordinary process memory.
+ *   - A stream argument is a hipStream_t passed as void*; NULL = the default stream.
+ *   - Return values: LEX_OK (0) or a negative LEX_E* code.  Errors are reported
+ *     synchronously only for invalid arguments; device-side outcomes (overflow, the
+ *     error offset) are written to the caller's lex_result in device memory.
+ *   - A lex_dfa is immutable after lex_compile and may be used concurrently from
+ *     several host threads and streams.
+ */
+#ifndef PAPER_LEX_H
+#define PAPER_LEX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  LEX_OK = 0,
+  LEX_EINVAL = -1,    /* bad argument (null pointer, bad mode, misaligned buffer, ...) */
+  LEX_ESYNTAX = -2,   /* a pattern does not parse                                     */
+  LEX_ENOMEM = -3,    /* host or device allocation failed                             */
+  LEX_EOVERFLOW = -4, /* more tokens than the output capacity (device-side status)     */
+  LEX_EDEVICE = -5,   /* a HIP call failed                                            */
+  LEX_ELIMIT = -6     /* > 255 kinds, too many states, workspace too small, n > 2^32-16 */
+};
+
+enum {
+  LEX_MODE_EXACT = 0,   /* cut at the exact map; output tok(w)                             */
+  LEX_MODE_DISCARD = 1, /* cut at the modulo-I map; output pi_I(tok(w)) (kept kinds only)  */
+  LEX_MODE_SERIAL = 2   /* one slice, one lane: the serial scan itself (testing, refusal)  */
+};
+
+typedef struct lex_dfa lex_dfa;
+
+/* One token definition (Section 3).  pattern: NUL-terminated byte regex (literals, '.',
+ * classes [..] [^..] with ranges, groups, '|', postfix * + ? {m} {m,} {m,n}, escapes
+ * \n \t \r \f \v \b \0 \xHH and a backslash before any non-alphanumeric byte).
+ * priority: lower wins a same-length tie, then the lower index.  discard: 1 if the kind is
+ * in I (used by LEX_MODE_DISCARD and the modulo-I map, Section 6.1). */
+typedef struct {
+  const char *pattern;
+  int32_t priority;
+  uint8_t discard;
+} lex_tokdef;
+
+/* Result of one scan, written by the device into caller memory. */
+typedef struct {
+  uint64_t ntokens;      /* tokens written; if status == LEX_EOVERFLOW, tokens required     */
+  uint64_t error_offset; /* con(w); == n iff the input is completely tokenizable             */
+  int32_t status;        /* LEX_OK or LEX_EOVERFLOW                                          */
+  uint32_t nslices;      /* non-empty slices the plan produced (1 for a serial scan)         */
+} lex_result;
+
+/* Compiled-automaton summary (host copy). */
+typedef struct {
+  int32_t nkinds;
+  int32_t nstates;    /* states of the trimmed, minimised live automaton (Section 4.1) */
+  int32_t nclasses;   /* byte classes of the transition table                         */
+  int32_t nrows;      /* rows of the packed device table                              */
+  int32_t reentrant;  /* Definition 1                                                 */
+  int32_t monotone;   /* 1: no live edge leaves an accepting state for a non-accepting
+                         one, so the walker never needs to fall back                  */
+  int32_t q0_live;    /* 0: the token set accepts nothing                             */
+  int32_t reserved;
+} lex_info_t;
+
+/* Compiles ndefs (1..255) definitions.  On success *out owns the host tables and their
+ * device copy (uploaded to the current HIP device) until lex_free.  On failure returns
+ * LEX_ESYNTAX/LEX_ELIMIT/LEX_EINVAL/LEX_EDEVICE and writes a message into err (errlen
+ * bytes, may be NULL). */
+int lex_compile(const lex_tokdef *defs, uint32_t ndefs, lex_dfa **out, char *err, size_t errlen);
+
+/* Builds a lexer from a hand-built automaton (the examples of Section 4.1): next is a
+ * host array of nstates*256 targets (-1 = undefined), accept[q] a token index in
+ * [0, ntok) or -1, discard[t] flags t in I (ntok entries, may be NULL for I empty).  The
+ * automaton is trimmed to Q+ and minimised exactly as a compiled one. */
+int lex_compile_table(int32_t nstates, int32_t q0, const int32_t *next, const int32_t *accept,
+                      const uint8_t *discard, int32_t ntok, lex_dfa **out, char *err, size_t errlen);
+
+/* Releases a lexer (host and device tables).  The caller must not have scans in flight. */
+void lex_free(lex_dfa *dfa);
+
+/* Useful certified set of a mode (host call): bits[b >> 3] bit (b & 7) is set iff byte b is
+ * a useful certified split byte (mode EXACT: Definition 2 with Corollary 2; DISCARD:
+ * Definition 3 with Proposition 2).  raw != 0 returns the maps before the useful filter
+ * (vacuous bytes included).  LEX_MODE_SERIAL returns the empty set. */
+int lex_cert(const lex_dfa *dfa, int mode, int raw, uint8_t bits[32]);
+
+int lex_info(const lex_dfa *dfa, lex_info_t *out);
+
+/* Host copy of the packed table of a mode: nrows*256 u32 entries (layout documented in
+ * the library source) and nrows row-info bytes; for host-side models in tests. */
+int lex_tables(const lex_dfa *dfa, int mode, uint32_t *table, size_t table_entries,
+               uint8_t *rowinfo, uint8_t *rowkind, size_t nrows);
+
+/* Tuning of one scan (NULL = defaults).  chunk_bytes: target length of the paper's
+ * equal-division chunks (boundaries slide forward to the next certified byte); lane_bytes:
+ * target length of the sub-slices one GPU lane walks (a multiple of 16 and a divisor of
+ * chunk_bytes; 0 = chosen from n).  path: 0 = default, 1 = the five-step pipeline
+ * (bitmap, plan, count walk, scan, emit walk), 2 = fused (each lane finds its own cut,
+ * no bitmap).  block_threads: threads per walk workgroup (0 = default; only 256 is
+ * supported).  events: optional array of LEX_NPHASES + 1 hipEvent_t (passed as void*,
+ * created by the caller) recorded on the scan's stream at the phase boundaries: [0] start,
+ * [1] after planning (steps a, b), [2] after the count walk (c), [3] after the scan (d),
+ * [4] after the emit walk (e). */
+enum { LEX_NPHASES = 4 };
+typedef struct {
+  uint64_t chunk_bytes;
+  uint32_t lane_bytes;
+  int32_t path;
+  int32_t block_threads;
+  int32_t reserved;
+  void *const *events;
+} lex_run_opts;
+
+/* Device workspace bytes lex_run needs for n input bytes under opts (NULL = defaults). */
+size_t lex_workspace_size(const lex_dfa *dfa, uint64_t n, int mode, const lex_run_opts *opts);
+
+/* Scans d_bytes[0, n) (device pointer) and writes, on `stream`, at most cap tokens:
+ * d_kinds[i] (device u8), d_lens[i] (device u32) and, when d_offsets is non-NULL,
+ * d_offsets[i] (device u64 start offset of token i in d_bytes).  *d_result (device pointer)
+ * receives the lex_result.  d_ws (device pointer, ws_bytes >= lex_workspace_size(...),
+ * 256-byte aligned) is scratch owned by the caller for the duration of the scan.
+ * cap = n is always sufficient.  The call only enqueues work; it returns LEX_EINVAL for
+ * bad arguments, LEX_ELIMIT for an oversized n or a short workspace, LEX_EDEVICE if a launch
+ * fails.  Outputs are unspecified when the result status is LEX_EOVERFLOW.  n must not
+ * exceed 2^32 - 16 (lengths and offsets inside one buffer are 32-bit on the device). */
+int lex_run(const lex_dfa *dfa, const uint8_t *d_bytes, uint64_t n, int mode, uint8_t *d_kinds,
+            uint32_t *d_lens, uint64_t *d_offsets, uint64_t cap, lex_result *d_result, void *d_ws,
+            size_t ws_bytes, const lex_run_opts *opts, void *stream);
+
+/* Certificate bitmap of step (a) on its own (device pointers): d_bits[i >> 6] bit (i & 63)
+ * is set iff byte d_bytes[i] is in the useful map of `mode`; ceil(n / 64) u64 words. */
+int lex_cert_bitmap(const lex_dfa *dfa, const uint8_t *d_bytes, uint64_t n, int mode, uint64_t *d_bits,
+                    void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PAPER_LEX_H */

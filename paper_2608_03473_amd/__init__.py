@@ -1,0 +1,17 @@
+"""MI355X-native certified-split lexer (gfx950 HIP kernels behind a small C ABI).
+
+The binding is argument marshalling only: every step of a scan runs in the HIP library
+``liblexgpu.so`` (built in-tree by ``paper_2608_03473_amd.build``).  PyTorch provides device
+memory and streams.  Importing the package does not touch the GPU; the library is loaded
+on first use and its absence is an error (there is no CPU fallback).
+
+    lx = Lexer.compile(defs)                 # defs: [(pattern, priority, discard), ...]
+    kinds, lens, err = lx.run(u8_cuda_tensor, mode=LEX_MODE_EXACT)
+"""
+from .abi import (LEX_EDEVICE, LEX_EINVAL, LEX_ELIMIT, LEX_ENOMEM, LEX_EOVERFLOW, LEX_ESYNTAX,  # noqa: F401
+                  LEX_MODE_DISCARD, LEX_MODE_EXACT, LEX_MODE_SERIAL, LEX_OK, LexError, RunOpts,
+                  lib, lib_path)
+from .lexer import Lexer, RunResult  # noqa: F401
+
+__all__ = ["Lexer", "RunResult", "RunOpts", "LexError", "lib", "lib_path",
+           "LEX_MODE_EXACT", "LEX_MODE_DISCARD", "LEX_MODE_SERIAL"]

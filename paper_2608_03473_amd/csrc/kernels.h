@@ -1,0 +1,74 @@
+// kernels.h -- launchers of the HIP kernels (gfx950).  Internal to the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace lexk {
+
+// Device-resident, read-only description of one compiled lexer in one mode.
+struct DevTable {
+  const uint32_t *table;   // nrows * 256 packed entries
+  const uint8_t *rowinfo;  // nrows
+  const uint8_t *rowkind;  // nrows
+  int nrows;
+  int row_sink;            // index
+  int row_fail;            // index, -1 if the automaton is monotone
+  int monotone;
+};
+
+// The useful certificate map of the scan's mode, in a form the bitmap kernel uses.
+struct CertMap {
+  uint32_t words[8];   // bit b: byte b is a useful certified byte
+  int nbytes;          // popcount
+  uint8_t bytes[8];    // the certified bytes themselves when nbytes <= 8
+};
+
+// Workspace carve-up for one scan (all device pointers).
+struct Plan {
+  uint32_t n;              // input bytes (< 2^32)
+  uint32_t lane_bytes;     // lane target length (multiple of 16)
+  uint32_t nlanes;         // M = ceil(n / lane_bytes), at least 1
+  uint32_t nblocks;        // walk workgroups
+  uint32_t block;          // threads per walk workgroup
+  uint64_t *bitmap;        // ceil(n / 64) words            (pipeline path)
+  uint64_t *tile_next;     // ntiles + 1 entries            (pipeline path)
+  uint32_t ntiles;         // ceil(n / 4096)
+  uint32_t *cuts;          // nlanes + 1 lane boundaries
+  uint64_t *counts;        // nlanes tokens per lane (counted kinds)
+  uint64_t *blk_sum;       // nblocks
+  uint32_t *blk_fail;      // nblocks: first halted lane of the block or ~0u
+  uint32_t *blk_nonempty;  // nblocks
+  uint32_t *meta;          // [0] = first halted lane or ~0u
+};
+
+size_t workspace_bytes(uint32_t n, uint32_t lane_bytes, uint32_t block, int pipeline);
+bool carve(void *ws, size_t ws_bytes, uint32_t n, uint32_t lane_bytes, uint32_t block, int pipeline,
+           Plan &p);
+
+struct ResultDev {  // mirrors lex_result
+  uint64_t ntokens;
+  uint64_t error_offset;
+  int32_t status;
+  uint32_t nslices;
+};
+
+hipError_t launch_bitmap(const uint8_t *in, uint32_t n, const CertMap &cm, uint64_t *bits, hipStream_t s);
+
+// Five-step pipeline: (a) bitmap, (b) plan, (c) count walk, (d) scan, (e) emit walk.
+// When the plan has one lane (serial mode, empty useful map) steps (a) and the tile
+// scan are skipped: the plan kernel then writes cuts = {0, n}.
+// ev: optional 5 events recorded at the phase boundaries (start, planned, counted,
+// scanned, emitted).
+hipError_t run_pipeline(const DevTable &t, const CertMap &cm, const uint8_t *in, const Plan &p,
+                        bool serial, uint8_t *kinds, uint32_t *lens, uint64_t *offs, uint64_t cap,
+                        ResultDev *res, hipStream_t s, hipEvent_t const *ev);
+// Fused: each lane places its own cut by a bounded search (no bitmap, no plan kernel).
+// cert_lut: device 256-byte 0/1 table of the useful map (the lanes search with it).
+hipError_t run_fused(const DevTable &t, const CertMap &cm, const uint8_t *cert_lut, const uint8_t *in,
+                     const Plan &p, bool serial, uint8_t *kinds, uint32_t *lens, uint64_t *offs, uint64_t cap,
+                     ResultDev *res, hipStream_t s, hipEvent_t const *ev);
+
+}  // namespace lexk

@@ -1,0 +1,300 @@
+// runtime.hip -- C ABI of the certified-split lexer (declared in include/lex.h).
+//
+// Host responsibilities: compile the token set (compile.cc), upload the packed tables
+// once per lexer, validate arguments, size and carve the caller's workspace, and enqueue
+// the kernels of kernels.hip on the caller's stream.  Nothing here touches the input
+// bytes: every step of a scan runs on the GPU.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/lex.h"
+#include "compile.h"
+#include "kernels.h"
+
+// Device copy of a lexer's tables on one HIP device.
+struct DevCopy {
+  int device = -1;
+  uint32_t *d_table[2] = {nullptr, nullptr};
+  uint8_t *d_rowinfo[2] = {nullptr, nullptr};
+  uint8_t *d_rowkind = nullptr;
+  uint8_t *d_cert_lut[2] = {nullptr, nullptr};  // 256-byte 0/1 useful maps
+};
+
+struct lex_dfa {
+  lexc::Compiled c;
+  lexk::CertMap cm[2];
+  std::vector<uint8_t> lut[2];
+  // Tables are uploaded once per device: eagerly by lex_compile when a device is
+  // present, otherwise by the first scan on that device.
+  std::mutex mu;
+  std::vector<DevCopy *> copies;
+};
+
+namespace {
+
+void set_err(char *err, size_t errlen, const std::string &m) {
+  if (err && errlen) snprintf(err, errlen, "%s", m.c_str());
+}
+
+bool bit(const uint8_t *m, int b) { return (m[b >> 3] >> (b & 7)) & 1; }
+
+template <class T>
+hipError_t upload(T **dst, const T *src, size_t count) {
+  hipError_t e = hipMalloc(reinterpret_cast<void **>(dst), std::max<size_t>(count, 1) * sizeof(T));
+  if (e != hipSuccess) return e;
+  return hipMemcpy(*dst, src, count * sizeof(T), hipMemcpyHostToDevice);
+}
+
+void free_copy(DevCopy *c) {
+  int cur = -1;
+  (void)hipGetDevice(&cur);
+  if (c->device >= 0) (void)hipSetDevice(c->device);
+  for (int m = 0; m < 2; ++m) {
+    if (c->d_table[m]) (void)hipFree(c->d_table[m]);
+    if (c->d_rowinfo[m]) (void)hipFree(c->d_rowinfo[m]);
+    if (c->d_cert_lut[m]) (void)hipFree(c->d_cert_lut[m]);
+  }
+  if (c->d_rowkind) (void)hipFree(c->d_rowkind);
+  if (cur >= 0) (void)hipSetDevice(cur);
+  delete c;
+}
+
+void release(lex_dfa *d) {
+  if (!d) return;
+  for (DevCopy *c : d->copies) free_copy(c);
+  delete d;
+}
+
+// Device copy of d's tables on the current device, uploading them on first use.
+DevCopy *device_copy(lex_dfa *d) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> g(d->mu);
+  for (DevCopy *c : d->copies)
+    if (c->device == dev) return c;
+  DevCopy *c = new DevCopy;
+  c->device = dev;
+  const lexc::Compiled &k = d->c;
+  hipError_t e = hipSuccess;
+  for (int m = 0; m < 2 && e == hipSuccess; ++m) {
+    e = upload(&c->d_table[m], k.table[m].data(), k.table[m].size());
+    if (e == hipSuccess) e = upload(&c->d_rowinfo[m], k.rowinfo[m].data(), k.rowinfo[m].size());
+    if (e == hipSuccess) e = upload(&c->d_cert_lut[m], d->lut[m].data(), d->lut[m].size());
+  }
+  if (e == hipSuccess) e = upload(&c->d_rowkind, k.rowkind.data(), k.rowkind.size());
+  if (e != hipSuccess) {
+    free_copy(c);
+    return nullptr;
+  }
+  d->copies.push_back(c);
+  return c;
+}
+
+int finish_compile(lex_dfa *d, lex_dfa **out, char *err, size_t errlen) {
+  const lexc::Compiled &c = d->c;
+  if ((size_t)c.nrows * 1024 + 2 * (size_t)c.nrows + 256 > 160 * 1024) {
+    set_err(err, errlen, "automaton too large for the LDS-resident table (" + std::to_string(c.nrows) + " rows)");
+    release(d);
+    return LEX_ELIMIT;
+  }
+  for (int m = 0; m < 2; ++m) {
+    const uint8_t *map = m == 0 ? c.exact_useful : c.discard_useful;
+    lexk::CertMap &cm = d->cm[m];
+    memset(&cm, 0, sizeof cm);
+    d->lut[m].assign(256, 0);
+    for (int b = 0; b < 256; ++b) {
+      d->lut[m][b] = bit(map, b);
+      if (d->lut[m][b]) {
+        cm.words[b >> 5] |= 1u << (b & 31);
+        if (cm.nbytes < 8) cm.bytes[cm.nbytes] = (uint8_t)b;
+        ++cm.nbytes;
+      }
+    }
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0 && !device_copy(d)) {
+    set_err(err, errlen, "device upload failed");
+    release(d);
+    return LEX_EDEVICE;
+  }
+  (void)hipGetLastError();  // a CPU-only host leaves a no-device error behind
+  *out = d;
+  return LEX_OK;
+}
+
+struct Resolved {
+  uint32_t lane_bytes;
+  uint32_t block;
+  int path;  // 1 pipeline, 2 fused
+  bool serial;
+  int table;  // 0 exact, 1 discard
+};
+
+uint32_t default_lane_bytes(uint64_t n) {
+  // Aim for about 256k lanes (one per lane slot of a full MI355X at 1024 threads per
+  // CU), between 64 B and 4 KiB.
+  uint64_t l = 64;
+  while (l < 4096 && n / l > (256u << 10)) l <<= 1;
+  return (uint32_t)l;
+}
+
+int resolve(const lex_dfa *d, uint64_t n, int mode, const lex_run_opts *o, Resolved &r) {
+  if (mode < 0 || mode > 3) return LEX_EINVAL;
+  r.table = mode & 1;
+  r.serial = (mode & 2) != 0 || d->cm[r.table].nbytes == 0;
+  r.path = o && o->path ? o->path : 1;
+  if (r.path != 1 && r.path != 2) return LEX_EINVAL;
+  r.block = o && o->block_threads ? (uint32_t)o->block_threads : 256u;
+  if (o && o->reserved) return LEX_EINVAL;
+  if (r.block != 256u) return LEX_EINVAL;  // kernels are compiled for 256-thread groups
+  uint32_t lb = o && o->lane_bytes ? o->lane_bytes : default_lane_bytes(n);
+  if (lb < 16 || (lb & 15)) return LEX_EINVAL;
+  if (o && o->chunk_bytes) {
+    if (o->chunk_bytes % lb) return LEX_EINVAL;  // lanes subdivide the paper's chunks
+  }
+  if (r.serial || n <= lb) lb = (uint32_t)std::max<uint64_t>(16, (n + 15) & ~15ull);  // one lane
+  if (r.serial && n > 0xFFFFFFF0ull) return LEX_ELIMIT;
+  r.lane_bytes = lb;
+  return LEX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lex_compile(const lex_tokdef *defs, uint32_t ndefs, lex_dfa **out, char *err, size_t errlen) {
+  if (!defs || !out || ndefs == 0) {
+    set_err(err, errlen, "null argument or no definitions");
+    return LEX_EINVAL;
+  }
+  *out = nullptr;
+  if (ndefs > 255) {
+    set_err(err, errlen, "at most 255 token definitions");
+    return LEX_ELIMIT;
+  }
+  std::vector<lexc::TokDef> v(ndefs);
+  for (uint32_t i = 0; i < ndefs; ++i) {
+    if (!defs[i].pattern) {
+      set_err(err, errlen, "null pattern");
+      return LEX_EINVAL;
+    }
+    v[i].pattern = defs[i].pattern;
+    v[i].priority = defs[i].priority;
+    v[i].discard = defs[i].discard != 0;
+  }
+  lex_dfa *d = new lex_dfa;
+  std::string msg;
+  if (!lexc::compile_defs(v, d->c, msg)) {
+    set_err(err, errlen, msg);
+    delete d;
+    return msg.find("exceeds") != std::string::npos || msg.find("too") != std::string::npos ? LEX_ELIMIT
+                                                                                            : LEX_ESYNTAX;
+  }
+  return finish_compile(d, out, err, errlen);
+}
+
+int lex_compile_table(int32_t nstates, int32_t q0, const int32_t *next, const int32_t *accept,
+                      const uint8_t *discard, int32_t ntok, lex_dfa **out, char *err, size_t errlen) {
+  if (!next || !accept || !out || ntok < 0 || ntok > 255) {
+    set_err(err, errlen, "bad argument");
+    return LEX_EINVAL;
+  }
+  *out = nullptr;
+  std::vector<uint8_t> disc((size_t)ntok, 0);
+  for (int t = 0; t < ntok; ++t) disc[t] = discard && discard[t] ? 1 : 0;
+  lex_dfa *d = new lex_dfa;
+  std::string msg;
+  if (!lexc::compile_table(nstates, q0, next, accept, disc, d->c, msg)) {
+    set_err(err, errlen, msg);
+    delete d;
+    return LEX_EINVAL;
+  }
+  return finish_compile(d, out, err, errlen);
+}
+
+void lex_free(lex_dfa *dfa) { release(dfa); }
+
+int lex_cert(const lex_dfa *d, int mode, int raw, uint8_t bits[32]) {
+  if (!d || !bits || mode < 0 || mode > 3) return LEX_EINVAL;
+  if (mode & 2) {
+    memset(bits, 0, 32);
+    return LEX_OK;
+  }
+  const lexc::Compiled &c = d->c;
+  const uint8_t *src = (mode & 1) ? (raw ? c.discard_raw : c.discard_useful) : (raw ? c.exact_raw : c.exact_useful);
+  memcpy(bits, src, 32);
+  return LEX_OK;
+}
+
+int lex_info(const lex_dfa *d, lex_info_t *o) {
+  if (!d || !o) return LEX_EINVAL;
+  const lexc::Compiled &c = d->c;
+  o->nkinds = c.nkinds;
+  o->nstates = c.q0_live ? c.dfa.nstates : 0;
+  o->nclasses = c.dfa.nclasses;
+  o->nrows = c.nrows;
+  o->reentrant = c.reentrant;
+  o->monotone = c.monotone;
+  o->q0_live = c.q0_live;
+  o->reserved = 0;
+  return LEX_OK;
+}
+
+int lex_tables(const lex_dfa *d, int mode, uint32_t *table, size_t table_entries, uint8_t *rowinfo,
+               uint8_t *rowkind, size_t nrows) {
+  if (!d || mode < 0 || mode > 1) return LEX_EINVAL;
+  const lexc::Compiled &c = d->c;
+  if (table_entries < c.table[mode].size() || nrows < (size_t)c.nrows) return LEX_ELIMIT;
+  if (table) memcpy(table, c.table[mode].data(), c.table[mode].size() * 4);
+  if (rowinfo) memcpy(rowinfo, c.rowinfo[mode].data(), c.nrows);
+  if (rowkind) memcpy(rowkind, c.rowkind.data(), c.nrows);
+  return LEX_OK;
+}
+
+size_t lex_workspace_size(const lex_dfa *d, uint64_t n, int mode, const lex_run_opts *opts) {
+  Resolved r;
+  if (!d || n > 0xFFFFFFF0ull || resolve(d, n, mode, opts, r) != LEX_OK) return 0;
+  return lexk::workspace_bytes((uint32_t)n, r.lane_bytes, r.block, r.path == 1);
+}
+
+int lex_run(const lex_dfa *d, const uint8_t *d_bytes, uint64_t n, int mode, uint8_t *d_kinds, uint32_t *d_lens,
+            uint64_t *d_offsets, uint64_t cap, lex_result *d_result, void *d_ws, size_t ws_bytes,
+            const lex_run_opts *opts, void *stream) {
+  if (!d || !d_result || (!d_bytes && n) || !d_ws) return LEX_EINVAL;
+  if (cap && (!d_kinds || !d_lens)) return LEX_EINVAL;
+  if (n > 0xFFFFFFF0ull) return LEX_ELIMIT;
+  Resolved r;
+  int rc = resolve(d, n, mode, opts, r);
+  if (rc != LEX_OK) return rc;
+  lexk::Plan p;
+  if (!lexk::carve(d_ws, ws_bytes, (uint32_t)n, r.lane_bytes, r.block, r.path == 1, p)) return LEX_ELIMIT;
+  const int m = r.table;
+  DevCopy *dc = device_copy(const_cast<lex_dfa *>(d));
+  if (!dc) return LEX_EDEVICE;
+  lexk::DevTable t{dc->d_table[m], dc->d_rowinfo[m], dc->d_rowkind, d->c.nrows, d->c.row_sink, d->c.row_fail,
+                   d->c.monotone ? 1 : 0};
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  auto *res = reinterpret_cast<lexk::ResultDev *>(d_result);
+  hipEvent_t const *ev = opts && opts->events ? reinterpret_cast<hipEvent_t const *>(opts->events) : nullptr;
+  hipError_t e = r.path == 1 ? lexk::run_pipeline(t, d->cm[m], d_bytes, p, r.serial, d_kinds, d_lens, d_offsets,
+                                                  cap, res, s, ev)
+                             : lexk::run_fused(t, d->cm[m], dc->d_cert_lut[m], d_bytes, p, r.serial, d_kinds,
+                                               d_lens, d_offsets, cap, res, s, ev);
+  return e == hipSuccess ? LEX_OK : LEX_EDEVICE;
+}
+
+int lex_cert_bitmap(const lex_dfa *d, const uint8_t *d_bytes, uint64_t n, int mode, uint64_t *d_bits,
+                    void *stream) {
+  if (!d || (!d_bytes && n) || (!d_bits && n) || mode < 0 || mode > 1) return LEX_EINVAL;
+  if (n > 0xFFFFFFF0ull) return LEX_ELIMIT;
+  hipError_t e = lexk::launch_bitmap(d_bytes, (uint32_t)n, d->cm[mode], d_bits, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? LEX_OK : LEX_EDEVICE;
+}
+
+}  // extern "C"

@@ -1,0 +1,177 @@
+"""Python face of the C ABI: compile a token set once, scan device buffers many times.
+
+Argument marshalling only -- torch tensors supply device memory and the current stream;
+every step of a scan runs in liblexgpu.so.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import abi
+
+
+def _norm_defs(defs):
+    out = []
+    for d in defs:
+        if hasattr(d, "pattern"):
+            pat, pr, dc = d.pattern, getattr(d, "priority", 0), getattr(d, "discard", False)
+        elif isinstance(d, dict):
+            pat, pr, dc = d["pattern"], d.get("priority", 0), d.get("discard", False)
+        else:
+            d = tuple(d)
+            pat, pr, dc = d[0], (d[1] if len(d) > 1 else 0), (d[2] if len(d) > 2 else False)
+        if isinstance(pat, str):
+            pat = pat.encode("latin-1")
+        out.append((pat, int(pr), bool(dc)))
+    return out
+
+
+def _bits_to_set(buf) -> frozenset:
+    b = bytes(buf)
+    return frozenset(i for i in range(256) if (b[i >> 3] >> (i & 7)) & 1)
+
+
+@dataclass
+class RunResult:
+    kinds: "object"          # torch.uint8 [ntokens] (device)
+    lens: "object"           # torch.int32 [ntokens] (device), u32 values
+    offsets: "object"        # torch.int64 [ntokens] (device) or None
+    ntokens: int
+    error_offset: int
+    status: int
+    nslices: int
+
+
+class Lexer:
+    """A compiled token set (lex_dfa)."""
+
+    def __init__(self, handle, ndefs: int, defs=None):
+        self._h = handle
+        self.ndefs = ndefs
+        self.defs = defs
+
+    # ----------------------------------------------------------------- build
+    @classmethod
+    def compile(cls, defs) -> "Lexer":
+        L = abi.lib()
+        nd = _norm_defs(defs)
+        arr = (abi.TokDef * len(nd))()
+        keep = []
+        for i, (p, pr, dc) in enumerate(nd):
+            keep.append(p)
+            arr[i].pattern = p
+            arr[i].priority = pr
+            arr[i].discard = 1 if dc else 0
+        h = C.c_void_p()
+        err = C.create_string_buffer(512)
+        rc = L.lex_compile(arr, len(nd), C.byref(h), err, 512)
+        abi.check(rc, err.value.decode("latin-1"))
+        return cls(h, len(nd), nd)
+
+    @classmethod
+    def from_table(cls, next_table, accept, q0: int = 0, discard=None) -> "Lexer":
+        L = abi.lib()
+        nxt = np.ascontiguousarray(np.asarray(next_table, dtype=np.int32))
+        acc = np.ascontiguousarray(np.asarray(accept, dtype=np.int32))
+        n = acc.size
+        assert nxt.shape == (n, 256)
+        ntok = int(acc.max()) + 1 if n and acc.max() >= 0 else 0
+        disc = np.zeros(max(ntok, 1), np.uint8)
+        if discard is not None:
+            d = np.asarray(discard, np.uint8)
+            ntok = max(ntok, d.size)
+            disc = np.zeros(max(ntok, 1), np.uint8)
+            disc[: d.size] = d
+        h = C.c_void_p()
+        err = C.create_string_buffer(512)
+        rc = L.lex_compile_table(n, q0, nxt.ctypes.data, acc.ctypes.data, disc.ctypes.data, ntok,
+                                 C.byref(h), err, 512)
+        abi.check(rc, err.value.decode("latin-1"))
+        return cls(h, ntok)
+
+    def close(self):
+        if getattr(self, "_h", None) and abi._lib is not None:
+            abi._lib.lex_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------- queries
+    def cert(self, mode: int = abi.LEX_MODE_EXACT, raw: bool = False) -> frozenset:
+        buf = (C.c_uint8 * 32)()
+        abi.check(abi.lib().lex_cert(self._h, mode, 1 if raw else 0, buf))
+        return _bits_to_set(buf)
+
+    def info(self) -> dict:
+        i = abi.Info()
+        abi.check(abi.lib().lex_info(self._h, C.byref(i)))
+        return {k: getattr(i, k) for k, _ in abi.Info._fields_ if k != "reserved"}
+
+    def tables(self, mode: int):
+        nrows = self.info()["nrows"]
+        t = np.empty(nrows * 256, np.uint32)
+        ri = np.empty(nrows, np.uint8)
+        rk = np.empty(nrows, np.uint8)
+        abi.check(abi.lib().lex_tables(self._h, mode, t.ctypes.data, t.size, ri.ctypes.data, rk.ctypes.data,
+                                       nrows))
+        return t, ri, rk
+
+    def workspace_size(self, n: int, mode: int, opts: abi.RunOpts | None = None) -> int:
+        ws = abi.lib().lex_workspace_size(self._h, n, mode, C.byref(opts) if opts else None)
+        if ws == 0:
+            raise abi.LexError(abi.LEX_EINVAL, "no workspace size for these arguments")
+        return ws
+
+    # ---------------------------------------------------------------- scans
+    def run_into(self, data, n: int, mode: int, kinds, lens, offsets, cap: int, result, ws,
+                 opts: abi.RunOpts | None = None, stream=None):
+        """Enqueues one scan into caller-owned device tensors (no allocation, no sync)."""
+        import torch
+
+        s = stream if stream is not None else torch.cuda.current_stream()
+        rc = abi.lib().lex_run(self._h, data.data_ptr() if n else None, n, mode,
+                               kinds.data_ptr() if cap else None, lens.data_ptr() if cap else None,
+                               offsets.data_ptr() if offsets is not None else None, cap,
+                               result.data_ptr(), ws.data_ptr(), ws.numel(),
+                               C.byref(opts) if opts else None, C.c_void_p(s.cuda_stream))
+        abi.check(rc, "lex_run")
+
+    def run(self, data, mode: int = abi.LEX_MODE_EXACT, offsets: bool = False, cap: int | None = None,
+            opts: abi.RunOpts | None = None) -> RunResult:
+        """Scans a 1-D uint8 CUDA tensor; synchronises once to read the result."""
+        import torch
+
+        if not (data.is_cuda and data.dtype == torch.uint8 and data.dim() == 1 and data.is_contiguous()):
+            raise abi.LexError(abi.LEX_EINVAL, "data must be a contiguous 1-D uint8 CUDA tensor")
+        n = data.numel()
+        dev = data.device
+        cap = n if cap is None else cap
+        kinds = torch.empty(max(cap, 1), dtype=torch.uint8, device=dev)
+        lens = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        offs = torch.empty(max(cap, 1), dtype=torch.int64, device=dev) if offsets else None
+        res = torch.zeros(3, dtype=torch.int64, device=dev)
+        ws = torch.empty(self.workspace_size(n, mode, opts), dtype=torch.uint8, device=dev)
+        self.run_into(data, n, mode, kinds, lens, offs, cap, res, ws, opts)
+        r = res.cpu().numpy()
+        ntok, err = int(r[0]), int(r[1])
+        status = int(np.int32(r[2] & 0xFFFFFFFF))
+        nsl = int((int(r[2]) >> 32) & 0xFFFFFFFF)
+        k = min(ntok, cap) if status == 0 else 0
+        return RunResult(kinds[:k], lens[:k], offs[:k] if offs is not None else None, ntok, err, status, nsl)
+
+    def cert_bitmap(self, data, mode: int = abi.LEX_MODE_EXACT):
+        import torch
+
+        n = data.numel()
+        bits = torch.zeros(max((n + 63) // 64, 1), dtype=torch.int64, device=data.device)
+        s = torch.cuda.current_stream()
+        abi.check(abi.lib().lex_cert_bitmap(self._h, data.data_ptr() if n else None, n, mode,
+                                            bits.data_ptr(), C.c_void_p(s.cuda_stream)))
+        return bits

@@ -1,0 +1,54 @@
+"""The C-ABI library loads and exports every function include/lex.h declares; argument
+checking that happens on the host.  CPU only: no scan is launched."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import paper_2608_03473_amd as P
+from workloads import tokensets as T
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared():
+    names = set()
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        if h.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", h)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names |= set(re.findall(r"^\s*(?:[\w\s\*]+?)\b(lex_\w+)\s*\(", src, flags=re.M))
+    return names
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared()
+    assert {"lex_compile", "lex_run", "lex_free", "lex_cert"} <= names
+    lib = C.CDLL(P.lib_path())
+    for name in sorted(names):
+        assert hasattr(lib, name), f"{name} declared but not exported"
+
+
+def test_host_side_argument_checks():
+    lx = P.Lexer.compile(T.as_tuples(T.CLIKE_L))
+    L = P.lib()
+    assert L.lex_workspace_size(lx._h, 1 << 20, 7, None) == 0  # bad mode
+    bad = P.RunOpts(lane_bytes=24)  # not a multiple of 16
+    assert L.lex_workspace_size(lx._h, 1 << 20, 0, C.byref(bad)) == 0
+    bad = P.RunOpts(lane_bytes=1024, chunk_bytes=1000)  # lanes must divide chunks
+    assert L.lex_workspace_size(lx._h, 1 << 20, 0, C.byref(bad)) == 0
+    assert L.lex_workspace_size(lx._h, 1 << 33, 0, None) == 0  # beyond 32-bit offsets
+    rc = L.lex_run(lx._h, None, 10, 0, None, None, None, 0, None, None, 0, None, None)
+    assert rc == P.LEX_EINVAL
+    assert lx.workspace_size(1 << 20, 0) > 0
+
+
+def test_info_and_tables():
+    lx = P.Lexer.compile(T.as_tuples(T.JSON))
+    info = lx.info()
+    assert info["monotone"] == 0 and info["nrows"] == info["nstates"] + 3
+    t, ri, rk = lx.tables(1)
+    assert t.size == info["nrows"] * 256 and ri.size == info["nrows"]
+    # every next-row field points at a row of the table
+    assert int(((t & 0xFFFFF) >> 8).max()) < info["nrows"]

@@ -1,0 +1,176 @@
+"""GPU parity: the HIP path through the C ABI against the oracle, element by element.
+
+Sizes the oracle finishes in seconds that still span many lanes, several 4 KiB bitmap
+tiles and ragged tails; both planner paths; several lane lengths; both modes; malformed
+inputs (Corollary 1's truncation and error offset); edge cases.  The bar is bit-exact
+kinds, lengths, offsets, token count and error offset.
+"""
+import random
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from workloads import tokensets as T
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_2608_03473_amd")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _needs_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+_LEX, _ORC = {}, {}
+
+
+def lexers(name):
+    if name not in _LEX:
+        defs = T.as_tuples(T.NAMED[name])
+        _LEX[name] = P.Lexer.compile(defs)
+        _ORC[name] = oracle.OracleSet(defs)
+    return _LEX[name], _ORC[name]
+
+
+def to_dev(buf, pad_front=0):
+    a = np.asarray(buf, dtype=np.uint8)
+    if not pad_front:
+        return torch.from_numpy(a.copy()).cuda()
+    big = torch.zeros(a.size + pad_front, dtype=torch.uint8, device="cuda")
+    big[pad_front:] = torch.from_numpy(a.copy()).cuda()
+    return big[pad_front:]
+
+
+def check(name, buf, mode, opts=None, pad_front=0, offsets=True, label=""):
+    lx, oc = lexers(name)
+    print(f"[case] {name} mode={mode} n={len(buf)} opts={opts and (opts.lane_bytes, opts.path)} "
+          f"pad={pad_front} {label}", flush=True)
+    k, l, o, con = oc.lex(bytes(buf), discard=bool(mode & 1), offsets=True)
+    r = lx.run(to_dev(buf, pad_front), mode=mode, offsets=offsets, opts=opts)
+    assert r.status == 0
+    assert r.error_offset == con, (r.error_offset, con)
+    assert r.ntokens == len(k), (r.ntokens, len(k))
+    np.testing.assert_array_equal(r.kinds.cpu().numpy(), k)
+    np.testing.assert_array_equal(r.lens.cpu().numpy().view(np.uint32), l)
+    if offsets:
+        np.testing.assert_array_equal(r.offsets.cpu().numpy().astype(np.uint64), o)
+    return r
+
+
+def opts(lane, path):
+    return P.RunOpts(lane_bytes=lane, path=path)
+
+
+CL = workloads.clike(1 << 20, 1)  # the 1 MiB config, seed 1
+
+
+@pytest.mark.parametrize("path", [1, 2])
+@pytest.mark.parametrize("lane", [16, 64, 256, 1024, 4096, 0])
+def test_clike_1mib_exact(path, lane):
+    r = check("clike_l", CL, P.LEX_MODE_EXACT, opts(lane, path))
+    assert r.nslices > 1
+
+
+@pytest.mark.parametrize("path", [1, 2])
+def test_clike_ragged_and_unaligned(path):
+    for n in (1, 15, 16, 17, 63, 64, 65, 4095, 4097, 70001):
+        for pad in (0, 3):
+            check("clike_l", CL[:n], P.LEX_MODE_EXACT, opts(16, path), pad_front=pad)
+
+
+def test_serial_mode_and_empty():
+    check("clike_l", CL[:200000], P.LEX_MODE_SERIAL)
+    r = check("clike_l", CL[:0], P.LEX_MODE_EXACT)
+    assert r.ntokens == 0 and r.error_offset == 0
+
+
+def _stray(buf, k, seed):
+    b = np.array(buf, copy=True)
+    rng = random.Random(seed)
+    for _ in range(k):
+        b[rng.randrange(b.size)] = 0x01
+    return b
+
+
+@pytest.mark.parametrize("path", [1, 2])
+def test_malformed_error_offset(path):
+    """Corollary 1: output truncated at the first halting slice, error offset = con(w)."""
+    base = CL[:300000]
+    for seed in range(8):
+        for lane in (16, 256):
+            check("clike_l", _stray(base, 1 + seed % 3, seed), P.LEX_MODE_EXACT, opts(lane, path), label=f"seed{seed}")
+    # an unterminated string and a lone '&'
+    for bad in (b'x = "abc\ny', b"a && b & c\n", b"\x01", b"ok\n\x01"):
+        buf = np.frombuffer(bytes(CL[:5000]) + bad + bytes(CL[5000:9000]), np.uint8)
+        check("clike_l", buf, P.LEX_MODE_EXACT, opts(64, path))
+
+
+@pytest.mark.parametrize("path", [1, 2])
+def test_discard_clike_d(path):
+    check("clike_d", CL, P.LEX_MODE_DISCARD, opts(256, path))
+    check("clike_d", CL, P.LEX_MODE_EXACT, opts(256, path))  # empty exact map: one slice
+
+
+@pytest.mark.parametrize("path", [1, 2])
+def test_json_discard(path):
+    js = workloads.json(2 << 20, 4)
+    r = check("json", js, P.LEX_MODE_DISCARD, opts(128, path))
+    assert r.nslices > 100
+    check("json", js[:300000], P.LEX_MODE_EXACT, opts(128, path))  # refused: one lane
+    # non-monotone fallbacks inside many lanes
+    bad = np.frombuffer(b"\n".join([b"1.", b"[1.5e]", b"-", b"1e+", b"tru", b"{\"a\": 1.}"] * 50), np.uint8)
+    check("json", bad, P.LEX_MODE_DISCARD, opts(16, path))
+
+
+def test_clike_b_refused():
+    cb = workloads.clike(400000, 9, bcomment=True)
+    r = check("clike_b", cb, P.LEX_MODE_DISCARD)
+    assert r.nslices == 1
+    check("clike_b", np.frombuffer(b"/* a\nb */ x /* y", np.uint8), P.LEX_MODE_DISCARD)
+
+
+def test_log_planning_workload():
+    w = workloads.loglines(1 << 20, 40)
+    r = check("log", w, P.LEX_MODE_EXACT, opts(1024, 1))
+    assert r.ntokens == 2 * ((1 << 20) // 40) + 1
+
+
+def test_overflow_status():
+    lx, oc = lexers("clike_l")
+    k, l, con = oc.lex(bytes(CL[:10000]))
+    r = lx.run(to_dev(CL[:10000]), cap=len(k) - 1)
+    assert r.status == P.LEX_EOVERFLOW and r.ntokens == len(k)
+    r = lx.run(to_dev(CL[:10000]), cap=len(k))
+    assert r.status == 0 and r.ntokens == len(k)
+
+
+def test_cert_bitmap_kernel():
+    lx, _ = lexers("json")
+    js = workloads.json(100003, 3)
+    bits = lx.cert_bitmap(to_dev(js), P.LEX_MODE_DISCARD).cpu().numpy().view(np.uint64)
+    want = np.isin(js, [9, 10, 13])
+    got = np.unpackbits(bits.view(np.uint8), bitorder="little")[: js.size].astype(bool)
+    np.testing.assert_array_equal(got, want)
+
+
+def test_random_sets_short_strings():
+    """Random token sets (the brute-force family) on short strings, one scan per string."""
+    from randsets import rand_set
+    rng = random.Random(4)
+    for seed in range(30):
+        defs = rand_set(seed, "abc")
+        lx, oc = P.Lexer.compile(defs), oracle.OracleSet(defs)
+        for _ in range(12):
+            w = bytes(rng.choice(b"abc") for _ in range(rng.randint(1, 40)))
+            for mode in (0, 1):
+                k, l, con = oc.lex(w, discard=bool(mode))
+                r = lx.run(to_dev(np.frombuffer(w, np.uint8)), mode=mode, opts=opts(16, 1 + (seed & 1)))
+                assert r.error_offset == con and r.ntokens == len(k), (defs, w, mode)
+                np.testing.assert_array_equal(r.kinds.cpu().numpy(), k)
+                np.testing.assert_array_equal(r.lens.cpu().numpy().view(np.uint32), l)
