@@ -34,6 +34,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle CPU time")
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--copy-ref", action="store_true",
+                    help="also run one plain device copy of n bytes (scale for HBM counters)")
     return ap.parse_args()
 
 
@@ -73,6 +75,13 @@ def main():
     ws = torch.empty(lx.workspace_size(n, mode, opts), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
 
+    if args.copy_ref:
+        # a plain shader copy (elementwise kernel: reads n bytes, writes n bytes), so the
+        # HBM counters of the scan can be scaled by what they read for a known copy
+        ref = torch.empty_like(data)
+        torch.bitwise_or(data, 0, out=ref)
+        torch.cuda.synchronize()
+        del ref
     for _ in range(args.warmup):
         lx.run_into(data, n, mode, kinds, lens, None, cap, res, ws, opts)
     torch.cuda.synchronize()

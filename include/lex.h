@@ -125,8 +125,8 @@ int lex_tables(const lex_dfa *dfa, int mode, uint32_t *table, size_t table_entri
  * target length of the sub-slices one GPU lane walks (a multiple of 16 and a divisor of
  * chunk_bytes; 0 = chosen from n).  path: 0 = default, 1 = the five-step pipeline
  * (bitmap, plan, count walk, scan, emit walk), 2 = fused (each lane finds its own cut,
- * no bitmap).  block_threads: threads per walk workgroup (0 = default; only 256 is
- * supported).  events: optional array of LEX_NPHASES + 1 hipEvent_t (passed as void*,
+ * no bitmap).  block_threads: threads per walk workgroup, 256, 512 or 1024 (0 = the
+ * largest whose LDS fits).  events: optional array of LEX_NPHASES + 1 hipEvent_t (passed as void*,
  * created by the caller) recorded on the scan's stream at the phase boundaries: [0] start,
  * [1] after planning (steps a, b), [2] after the count walk (c), [3] after the scan (d),
  * [4] after the emit walk (e). */
@@ -146,7 +146,8 @@ size_t lex_workspace_size(const lex_dfa *dfa, uint64_t n, int mode, const lex_ru
 /* Scans d_bytes[0, n) (device pointer) and writes, on `stream`, at most cap tokens:
  * d_kinds[i] (device u8), d_lens[i] (device u32) and, when d_offsets is non-NULL,
  * d_offsets[i] (device u64 start offset of token i in d_bytes).  *d_result (device pointer)
- * receives the lex_result.  d_ws (device pointer, ws_bytes >= lex_workspace_size(...),
+ * receives the lex_result.  d_kinds and d_lens must be 16-byte aligned (outputs leave the
+ * kernels in 16-byte chunks).  d_ws (device pointer, ws_bytes >= lex_workspace_size(...),
  * 256-byte aligned) is scratch owned by the caller for the duration of the scan.
  * cap = n is always sufficient.  The call only enqueues work; it returns LEX_EINVAL for
  * bad arguments, LEX_ELIMIT for an oversized n or a short workspace, LEX_EDEVICE if a launch

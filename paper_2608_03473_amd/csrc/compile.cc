@@ -642,9 +642,9 @@ void pack(Compiled &R) {
   R.row_sink = 1 + S;
   R.row_fail = R.monotone ? -1 : 2 + S;
   R.nrows = R.monotone ? 2 + S : 3 + S;
-  const uint32_t sink = (uint32_t)R.row_sink * 256u;
-  const uint32_t fail = R.monotone ? sink : (uint32_t)R.row_fail * 256u;
-  auto row_of = [](int q) { return (uint32_t)(1 + q) * 256u; };
+  const uint32_t sink = row_state(R.row_sink);
+  const uint32_t fail = R.monotone ? sink : row_state(R.row_fail);
+  auto row_of = [](int q) { return row_state(1 + q); };
   R.rowkind.assign(R.nrows, 0xFF);
   for (int q = 0; q < S; ++q)
     if (d.acc[q] >= 0) R.rowkind[1 + q] = (uint8_t)d.acc[q];
@@ -653,10 +653,11 @@ void pack(Compiled &R) {
     std::vector<uint32_t> &T = R.table[mode];
     T.assign((size_t)R.nrows * 256, 0);
     auto enter = [&](int t) { return row_of(t) | (d.acc[t] >= 0 ? kAcc : 0u); };
+    auto at = [&](int row, int b) -> uint32_t & { return T[(size_t)row * 256 + (b ^ row_swizzle(row))]; };
     for (int b = 0; b < 256; ++b) {
       const int c = d.cls[b];
       const int t0 = S ? d.next[c] : -1;
-      T[b] = t0 >= 0 ? enter(t0) : sink;
+      at(0, b) = t0 >= 0 ? enter(t0) : sink;
       for (int q = 0; q < S; ++q) {
         const int t = d.next[(size_t)q * d.nclasses + c];
         uint32_t e;
@@ -668,10 +669,10 @@ void pack(Compiled &R) {
         } else {
           e = fail;
         }
-        T[(size_t)(1 + q) * 256 + b] = e;
+        at(1 + q, b) = e;
       }
-      T[(size_t)R.row_sink * 256 + b] = sink;
-      if (!R.monotone) T[(size_t)R.row_fail * 256 + b] = fail;
+      at(R.row_sink, b) = sink;
+      if (!R.monotone) at(R.row_fail, b) = fail;
     }
     std::vector<uint8_t> &I = R.rowinfo[mode];
     I.assign(R.nrows, 0);
@@ -695,7 +696,7 @@ bool finish(Compiled &R, const Dfa &raw, std::string &err) {
     certify(R);
   }
   pack(R);
-  if ((size_t)R.nrows * 256 > kNextMask) {
+  if (R.nrows > kMaxRows) {
     err = "too many states for the packed table";
     return false;
   }

@@ -17,24 +17,32 @@
 namespace lexc {
 
 // Packed-table entry layout (one u32 per (row, byte)):
-//   bits  0..19  next row * 256 (index of the next row's first entry)
-//   bits 20..27  token kind emitted by this step (valid when EMIT is set)
-//   bit  28      ACC: the next row is an accepting DFA state
-//   bit  30      EMIT: a token ends immediately before this byte; the byte then
-//                starts the next token (the step already moved to delta(q0, byte))
-//   bit  31      COUNT: EMIT of a kind that is written in this mode
+//   bit  0       COUNT: a token of a kind written in this mode ends before this byte
+//   bit  1       EMIT: a token ends immediately before this byte; the byte then starts
+//                the next token (the step has already moved to delta(q0, byte))
+//   bits 2..6    swizzle of the next row, (row & 31)
+//   bit  7       ACC: the next row is an accepting DFA state
+//   bits 10..23  byte offset of the next row in the table (row index * 1024)
+//   bits 24..31  token kind emitted by this step (valid when EMIT is set)
+// The walk state is the entry masked to bits 2..6 and 10..23, and the entry for byte b
+// of that row sits at LDS byte address state ^ (b << 2): row r stores byte b's entry at
+// index r * 256 + (b ^ (r & 31)), so lanes reading the same byte in different rows hit
+// different LDS banks.
 // Rows: 0 = token start (q0 before any byte of the token), 1 + q = DFA state q,
 //       then SINK (halted; absorbs everything) and, for non-monotone automata,
 //       FAIL (a dead end after a non-accepting state: the walker must fall back to
 //       the last accepting position).
-constexpr uint32_t kNextMask = 0xFFFFFu;
-constexpr int kKindShift = 20;
-constexpr uint32_t kAcc = 1u << 28;
-constexpr uint32_t kEmit = 1u << 30;
-constexpr uint32_t kCount = 1u << 31;
-constexpr uint32_t kRowStart = 0;
-// rowinfo byte: bit 7 = accepting, bit 6 = counted in this mode, bits 0..5 unused;
-// the accepting kind is in rowkind[].
+constexpr uint32_t kCount = 1u << 0;
+constexpr uint32_t kEmit = 1u << 1;
+constexpr uint32_t kAcc = 1u << 7;
+constexpr uint32_t kStateMask = 0x00FFFC7Cu;
+constexpr int kRowShift = 10;
+constexpr int kKindShift = 24;
+constexpr int kMaxRows = 1 << 14;
+inline uint32_t row_swizzle(int row) { return (uint32_t)row & 31u; }
+inline uint32_t row_state(int row) { return ((uint32_t)row << kRowShift) | (row_swizzle(row) << 2); }
+// rowinfo byte: bit 7 = accepting, bit 6 = counted in this mode; the accepting kind is
+// in rowkind[].
 constexpr uint8_t kInfoAcc = 0x80;
 constexpr uint8_t kInfoCount = 0x40;
 

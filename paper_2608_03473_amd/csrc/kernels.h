@@ -35,9 +35,11 @@ struct Plan {
   uint32_t block;          // threads per walk workgroup
   uint64_t *bitmap;        // ceil(n / 64) words            (pipeline path)
   uint64_t *tile_next;     // ntiles + 1 entries            (pipeline path)
+  uint64_t *tile_group;    // one per 1024 tiles             (pipeline path)
   uint32_t ntiles;         // ceil(n / 4096)
   uint32_t *cuts;          // nlanes + 1 lane boundaries
-  uint64_t *counts;        // nlanes tokens per lane (counted kinds)
+  uint32_t *counts;        // nlanes tokens per lane (counted kinds)
+  uint32_t *ends;          // nlanes slice ends (fused path; cuts holds the starts)
   uint64_t *blk_sum;       // nblocks
   uint32_t *blk_fail;      // nblocks: first halted lane of the block or ~0u
   uint32_t *blk_nonempty;  // nblocks
@@ -45,6 +47,9 @@ struct Plan {
 };
 
 size_t workspace_bytes(uint32_t n, uint32_t lane_bytes, uint32_t block, int pipeline);
+// Dynamic LDS of a walk workgroup: the table, its row info and, for the emit walk, a
+// 96-byte token ring per lane.
+size_t walk_lds_bytes(int nrows, uint32_t block, bool emit);
 bool carve(void *ws, size_t ws_bytes, uint32_t n, uint32_t lane_bytes, uint32_t block, int pipeline,
            Plan &p);
 

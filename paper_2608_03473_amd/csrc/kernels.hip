@@ -5,38 +5,48 @@
 //                    certificate map of the mode (SWAR compares when the map holds at
 //                    most 8 bytes, an LDS lookup otherwise); a wavefront ballot yields
 //                    the first certified byte of every 4 KiB tile.
-//   (b) k_tiles +    the equal-division planner of Section 6, one pass: every lane
+//   (b) k_tiles_* +  the equal-division planner of Section 6 in one pass: every lane
 //       k_plan       target j*lane_bytes slides forward to the next certified byte
-//                    (bitmap words inside its tile, then a suffix minimum over tiles);
-//                    duplicate slides give empty lanes, a target with nothing after it
-//                    gives the end of the input.  An empty useful map gives one slice.
-//   (c) k_walk<COUNT> every lane runs the longest-match loop of Section 3 on its slice
+//                    (bitmap words inside its tile, then a two-level suffix minimum over
+//                    tiles); duplicate slides give empty lanes and a target with nothing
+//                    after it gives the end of the input.  An empty useful map gives one
+//                    slice.
+//   (c) k_count      every lane runs the longest-match loop of Section 3 on its slice
 //                    [cut_j, cut_j+1) from the start row, treating the slice end as the end
 //                    of the input; the packed transition table lives in LDS.
 //   (d) k_scan       exclusive prefix of the per-lane counts; the first lane whose walk
 //                    halted fixes the output length and, by Corollary 1, truncates it.
-//   (e) k_walk<EMIT> every lane up to the first halted one walks again and writes its
+//   (e) k_emit       every lane up to the first halted one walks again and writes its
 //                    (kind, length[, offset]) triples at its prefix offset, skipping
 //                    discarded kinds in modulo-I mode (the image pi_I of Section 5).
+//                    Tokens are staged in a 64-byte per-lane LDS ring and leave in whole,
+//                    aligned 32-byte sectors (8 lengths or 32 kinds at a time), so the
+//                    emit walk issues few, full-width memory requests.
 //
-// Table entries (see compile.h): next row index * 256 in bits 0..19, kind in 20..27,
-// ACC (28), EMIT (30), COUNT (31).  Row 0 is the token start, SINK absorbs after a halt,
-// FAIL (non-monotone automata only) marks a dead end that must fall back to the last
-// accepting position.
+// Table entries (layout in compile.h): COUNT (bit 0), EMIT (bit 1), the next row's
+// swizzle (bits 2..6), ACC (bit 7), the next row's byte offset in bits 10..23 and the
+// emitted kind in bits 24..31.  The walk state is the entry masked to the row offset and
+// swizzle, so the next entry's LDS address is (e & kRowMask) ^ (b << 2).
+// Row 0 is the token start, SINK absorbs after a halt, FAIL (non-monotone automata only)
+// marks a dead end that falls back to the last accepting position.
 #include "kernels.h"
 
 namespace lexk {
 namespace {
 
-constexpr uint32_t kNextMask = 0xFFFFFu;
-constexpr uint32_t kAcc = 1u << 28;
-constexpr uint32_t kEmit = 1u << 30;
+constexpr uint32_t kCountBit = 1u << 0;
+constexpr uint32_t kEmitBit = 1u << 1;
+constexpr uint32_t kAccBit = 1u << 7;
+constexpr uint32_t kRowMask = 0x00FFFC7Cu;  // next row offset and its swizzle
+constexpr int kRowShift = 10;
 constexpr uint8_t kInfoAcc = 0x80;
 constexpr uint8_t kInfoCount = 0x40;
 constexpr uint32_t kNone = 0xFFFFFFFFu;
-constexpr uint32_t kTile = 4096;  // bytes per bitmap tile (64 words)
+constexpr uint32_t kTile = 4096;        // bytes per bitmap tile (64 words)
+constexpr uint32_t kTilesPerBlock = 1024;
 
 __host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+__host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
 
 // ------------------------------------------------------------- (a) bitmap
 // Per-byte zero test of a 32-bit word: bit 7 of each byte of the result is set iff
@@ -97,8 +107,8 @@ __global__ void __launch_bounds__(256) k_bitmap(const uint8_t *__restrict__ in, 
     }
     bits[wi] = word;
   }
-  // First certified byte of this wave's tile (tile index == global wave index).
   if (!tile_first) return;
+  // First certified byte of this wave's tile (tile index == global wave index).
   const uint64_t any = __ballot(word != 0);
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t tile = wi >> 6;
@@ -112,137 +122,253 @@ __global__ void __launch_bounds__(256) k_bitmap(const uint8_t *__restrict__ in, 
 }
 
 // --------------------------------------------------------------- (b) plan
-// Suffix minimum over tiles: tile_next[t] = first certified byte at or after tile t
-// (~0 if none); tile_next[ntiles] = ~0.  One workgroup of 1024 threads.
-__global__ void __launch_bounds__(1024) k_tiles(uint64_t *__restrict__ t, uint32_t ntiles) {
-  __shared__ uint64_t part[1024];
-  const uint32_t tid = threadIdx.x, nt = blockDim.x;
-  const uint32_t per = (ntiles + nt - 1) / nt;
-  const uint32_t lo = min(ntiles, tid * per), hi = min(ntiles, lo + per);
-  uint64_t m = ~0ull;
-  for (uint32_t i = lo; i < hi; ++i) m = min(m, t[i]);
-  part[tid] = m;
+// Two-level suffix minimum over tiles.  Level 1: in-block suffix minimum of each group
+// of kTilesPerBlock tiles (in place) and the group minimum.  Level 2: one workgroup
+// turns the group minima into exclusive suffix minima (min over later groups).
+__global__ void __launch_bounds__(1024) k_tiles_blocks(uint64_t *__restrict__ t, uint32_t ntiles,
+                                                       uint64_t *__restrict__ grp) {
+  __shared__ uint64_t part[kTilesPerBlock];
+  const uint32_t tid = threadIdx.x;
+  const uint32_t i = blockIdx.x * kTilesPerBlock + tid;
+  part[tid] = i < ntiles ? t[i] : ~0ull;
   __syncthreads();
-  // inclusive suffix-min scan over part[] (Hillis-Steele)
-  for (uint32_t d = 1; d < nt; d <<= 1) {
-    uint64_t v = tid + d < nt ? part[tid + d] : ~0ull;
+  for (uint32_t d = 1; d < kTilesPerBlock; d <<= 1) {
+    uint64_t v = tid + d < kTilesPerBlock ? part[tid + d] : ~0ull;
     __syncthreads();
     part[tid] = min(part[tid], v);
     __syncthreads();
   }
-  uint64_t run = tid + 1 < nt ? part[tid + 1] : ~0ull;
-  for (uint32_t i = hi; i > lo; --i) {
-    run = min(run, t[i - 1]);
-    t[i - 1] = run;
+  if (i < ntiles) t[i] = part[tid];
+  if (tid == 0) grp[blockIdx.x] = part[0];
+}
+
+__global__ void __launch_bounds__(1024) k_tiles_top(uint64_t *__restrict__ grp, uint32_t ngroups) {
+  __shared__ uint64_t part[1024];
+  const uint32_t tid = threadIdx.x;
+  part[tid] = tid < ngroups ? grp[tid] : ~0ull;
+  __syncthreads();
+  for (uint32_t d = 1; d < 1024; d <<= 1) {
+    uint64_t v = tid + d < 1024 ? part[tid + d] : ~0ull;
+    __syncthreads();
+    part[tid] = min(part[tid], v);
+    __syncthreads();
   }
-  if (tid == 0) t[ntiles] = ~0ull;
+  if (tid < ngroups) grp[tid] = tid + 1 < 1024 ? part[tid + 1] : ~0ull;  // exclusive
+}
+
+// First certified byte at or after the start of tile t (~0 if none).
+__device__ __forceinline__ uint64_t tile_next(const uint64_t *tn, const uint64_t *grp, uint32_t t,
+                                              uint32_t ntiles) {
+  if (t >= ntiles) return ~0ull;
+  return min(tn[t], grp[t / kTilesPerBlock]);
 }
 
 // cuts[j] = first certified byte at or after j*lane_bytes (n if none), cuts[0] = 0,
 // cuts[M] = n.  Non-decreasing; equal neighbours make empty lanes.
-__global__ void __launch_bounds__(256) k_plan(const uint64_t *__restrict__ bits, const uint64_t *__restrict__ tile_next,
-                                              uint32_t n, uint32_t lane_bytes, uint32_t nlanes,
-                                              uint32_t *__restrict__ cuts) {
+__global__ void __launch_bounds__(256) k_plan(const uint64_t *__restrict__ bits, const uint64_t *__restrict__ tn,
+                                              const uint64_t *__restrict__ grp, uint32_t n, uint32_t lane_bytes,
+                                              uint32_t nlanes, uint32_t *__restrict__ cuts) {
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j > nlanes) return;
-  if (j == 0) {
-    cuts[0] = 0;
-    return;
-  }
-  if (j == nlanes) {
-    cuts[nlanes] = n;
+  if (j == 0 || j == nlanes) {
+    cuts[j] = j ? n : 0;
     return;
   }
   const uint64_t x = (uint64_t)j * lane_bytes;
   uint64_t cut = n;
   if (x < n) {
     const uint32_t nwords = (n + 63) / 64;
+    const uint32_t ntiles = (n + kTile - 1) / kTile;
     uint32_t w = (uint32_t)(x >> 6);
     uint64_t m = bits[w] & (~0ull << (x & 63));
     const uint32_t tile_end = min(nwords, (w | 63u) + 1);
     while (!m && ++w < tile_end) m = bits[w];
-    if (m) {
-      cut = (uint64_t)w * 64 + (__ffsll((unsigned long long)m) - 1);
-    } else {
-      const uint64_t t = tile_next[(x >> 12) + 1];
-      cut = t < n ? t : n;
-    }
+    if (m) cut = (uint64_t)w * 64 + (__ffsll((unsigned long long)m) - 1);
+    else cut = min<uint64_t>(tile_next(tn, grp, (uint32_t)(x >> 12) + 1, ntiles), n);
   }
   cuts[j] = (uint32_t)min<uint64_t>(cut, n);
 }
 
 // ----------------------------------------------------------- (c), (e) walk
 struct Tables {
-  const uint32_t *T;      // LDS
-  const uint8_t *info;    // LDS
-  const uint8_t *kind;    // LDS
-  uint32_t sink, fail;    // row index * 256
+  const uint32_t *T;    // LDS, at LDS address 0
+  const uint8_t *info;  // LDS
+  const uint8_t *kind;  // LDS
+  uint32_t sink, fail;  // row byte offsets (fail == sink when monotone)
 };
 
-struct Out {
-  uint8_t *kinds;
-  uint32_t *lens;
-  uint64_t *offs;
-  uint64_t o, lim;        // next slot, end of this lane's slots
-  bool write;
-};
-
-struct LaneState {
-  uint32_t st;    // current row * 256
-  uint32_t tok;   // start of the current token
-  uint32_t lacc;  // position after the last accepting step (non-monotone)
-  uint32_t lrow;  // row * 256 of that accepting state
-  uint64_t cnt;   // counted tokens
-};
-
-template <bool EMIT>
-__device__ __forceinline__ void put(LaneState &L, Out &o, uint32_t kind, uint32_t end) {
-  if (EMIT) {
-    if (o.write && o.o < o.lim) {
-      o.kinds[o.o] = (uint8_t)kind;
-      o.lens[o.o] = end - L.tok;
-      if (o.offs) o.offs[o.o] = L.tok;
-    }
-    ++o.o;
-  }
-  ++L.cnt;
+__device__ __forceinline__ uint32_t entry(const Tables &tb, uint32_t st, uint32_t b) {
+  return *reinterpret_cast<const uint32_t *>(reinterpret_cast<const uint8_t *>(tb.T) + (st ^ (b << 2)));
 }
 
-// One transition on byte b at position p.
-template <bool EMIT, bool MONO>
-__device__ __forceinline__ void step(LaneState &L, Out &o, const Tables &tb, uint32_t b, uint32_t p) {
-  const uint32_t e = tb.T[L.st + b];
-  if (EMIT || !MONO) {
-    if (e & kEmit) {
-      if ((int32_t)e < 0) put<EMIT>(L, o, (e >> 20) & 0xFF, p);
-      L.tok = p;
-    }
-  } else {
-    L.cnt += e >> 31;
+// Emit-side per-lane state.  The lane owns output slots [first, first + count).
+//
+// Packed path (lanes shorter than 2^24 bytes, so every length fits 24 bits): each byte
+// step writes one word (length << 8 | kind) into a 16-slot LDS ring whether or not a
+// token ends there, and a kept token advances the slot.  Chunks of 8 kept tokens are
+// split off at most once per 8 bytes: the 8 lengths leave as one whole 32-byte sector
+// (two 16-byte stores) and the 8 kinds go to a 32-byte LDS stage that leaves as one
+// sector every 32 tokens.  A chunk that reaches below `first` (the lane's head) is
+// written slot by slot, as are the lane's incomplete last chunks.  Between two splits
+// at most 15 words are pending, so the 16 slots never overrun.
+//
+// Direct path (lanes of 2^24 bytes or more): every kept token is stored on the spot.
+constexpr int kSlots = 16;      // packed words in the ring
+constexpr int kChunk = 8;       // lengths per 32-byte sector
+constexpr int kKindSlots = 32;  // kinds per 32-byte sector
+// The workgroup's rings are stored slot-major: dword d of lane t sits at
+// (d * blockDim + t) * 4, so the lanes of a wave touch consecutive banks whatever
+// slots they write.  Per lane: 16 words, then 8 dwords of staged kinds.
+constexpr int kRingDwords = kSlots + kKindSlots / 4;  // 24
+constexpr int kRingBytes = 4 * kRingDwords;
+
+struct Ring {
+  uint32_t *w;        // LDS: dword d of this lane's ring is w[d * stride]
+  uint32_t stride;    // blockDim
+  uint8_t *kinds;     // global outputs (16-byte aligned)
+  uint32_t *lens;
+  uint64_t *offs;     // optional
+  uint32_t o;         // next output slot
+  uint32_t fl;        // slots below fl have been split off (a multiple of kChunk)
+  uint32_t first;     // the lane's first slot
+  bool write;
+  bool direct;
+};
+
+__device__ __forceinline__ uint32_t &ring_at(Ring &r, uint32_t d) { return r.w[d * r.stride]; }
+
+__device__ __forceinline__ uint32_t pack_word(uint32_t e, uint32_t len) {
+  // byte 0 <- byte 3 of e (the kind), bytes 1..3 <- bytes 0..2 of len
+  return __builtin_amdgcn_perm(e, len, 0x02010007u);
+}
+
+// Splits the chunk [r.fl, r.fl + 8) off the ring.
+__device__ __forceinline__ void ring_split(Ring &r) {
+  const uint32_t c0 = r.fl;
+  const uint32_t base = c0 & (kSlots - 1);
+  uint32_t wd[kChunk];
+#pragma unroll
+  for (int i = 0; i < kChunk; ++i) wd[i] = ring_at(r, base + i);
+  // kinds: byte 0 of each word, packed 4 to a dword, staged after the words
+  const uint32_t k0 = __builtin_amdgcn_perm(__builtin_amdgcn_perm(wd[3], wd[2], 0x0c0c0400u),
+                                            __builtin_amdgcn_perm(wd[1], wd[0], 0x0c0c0400u), 0x05040100u);
+  const uint32_t k1 = __builtin_amdgcn_perm(__builtin_amdgcn_perm(wd[7], wd[6], 0x0c0c0400u),
+                                            __builtin_amdgcn_perm(wd[5], wd[4], 0x0c0c0400u), 0x05040100u);
+  ring_at(r, kSlots + (c0 & (kKindSlots - 1)) / 4) = k0;
+  ring_at(r, kSlots + (c0 & (kKindSlots - 1)) / 4 + 1) = k1;
+  const uint4 la = make_uint4(wd[0] >> 8, wd[1] >> 8, wd[2] >> 8, wd[3] >> 8);
+  const uint4 lb = make_uint4(wd[4] >> 8, wd[5] >> 8, wd[6] >> 8, wd[7] >> 8);
+  if (c0 >= r.first) {
+    uint4 *dst = reinterpret_cast<uint4 *>(r.lens + c0);
+    dst[0] = la;
+    dst[1] = lb;
+  } else {  // the lane's head: only slots >= first are the lane's
+#pragma unroll
+    for (int i = 0; i < kChunk; ++i)
+      if (c0 + i >= r.first) r.lens[c0 + i] = wd[i] >> 8;
   }
-  L.st = e & kNextMask;
-  if (!MONO && (e & kAcc)) {
+  r.fl = c0 + kChunk;
+  if ((r.fl & (kKindSlots - 1)) == 0) {
+    const uint32_t k32 = r.fl - kKindSlots;
+    uint32_t kd[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) kd[i] = ring_at(r, kSlots + i);
+    if (k32 >= r.first) {
+      uint4 *dst = reinterpret_cast<uint4 *>(r.kinds + k32);
+      dst[0] = make_uint4(kd[0], kd[1], kd[2], kd[3]);
+      dst[1] = make_uint4(kd[4], kd[5], kd[6], kd[7]);
+    } else {
+      for (uint32_t i = r.first - k32; i < kKindSlots; ++i) r.kinds[k32 + i] = (uint8_t)(kd[i / 4] >> (8 * (i & 3)));
+    }
+  }
+}
+
+__device__ __forceinline__ void ring_maybe_split(Ring &r) {
+  if (r.write && r.o - r.fl >= kChunk) ring_split(r);
+}
+
+// Records the token whose word is in slot r.o as kept.
+__device__ __forceinline__ void ring_commit(Ring &r, uint32_t kind, uint32_t len, uint32_t start) {
+  if (r.write) {
+    if (r.direct) {
+      r.kinds[r.o] = (uint8_t)kind;
+      r.lens[r.o] = len;
+    }
+    if (r.offs) r.offs[r.o] = start;
+  }
+  ++r.o;
+  if (!r.direct) ring_maybe_split(r);
+}
+
+// The lane's incomplete last chunks, slot by slot (slots below first are skipped).
+__device__ __forceinline__ void ring_flush_tail(Ring &r) {
+  if (!r.write || r.direct) return;
+  for (uint32_t i = max(r.fl & ~(uint32_t)(kKindSlots - 1), r.first); i < max(r.fl, r.first); ++i) {
+    const uint32_t q = i & (kKindSlots - 1);
+    r.kinds[i] = (uint8_t)(ring_at(r, kSlots + q / 4) >> (8 * (q & 3)));
+  }
+  for (uint32_t i = max(r.fl, r.first); i < r.o; ++i) {
+    const uint32_t wd = ring_at(r, i & (kSlots - 1));
+    r.kinds[i] = (uint8_t)(wd & 0xFF);
+    r.lens[i] = wd >> 8;
+  }
+}
+
+__device__ __forceinline__ void ring_put(Ring &r, uint32_t kind, uint32_t len, uint32_t start) {
+  if (!r.direct) ring_at(r, r.o & (kSlots - 1)) = (len << 8) | kind;
+  ring_commit(r, kind, len, start);
+}
+
+struct LaneState {
+  uint32_t st;    // current row byte offset
+  uint32_t tok;   // start of the current token
+  uint32_t lacc;  // position after the last accepting step (non-monotone)
+  uint32_t lrow;  // row byte offset of that accepting state
+  uint32_t cnt;   // counted tokens (count walk)
+};
+
+// One transition on byte b at position p.  Emit walk: the step writes the candidate
+// token into the next ring slot unconditionally (a later step overwrites it unless the
+// token is kept), so only the chunk write-out is a branch.
+template <bool EMIT, bool MONO>
+__device__ __forceinline__ void step(LaneState &L, Ring &r, const Tables &tb, uint32_t b, uint32_t p) {
+  const uint32_t e = entry(tb, L.st, b);
+  if (EMIT) {
+    const uint32_t len = p - L.tok;
+    if (!r.direct) ring_at(r, r.o & (kSlots - 1)) = pack_word(e, len);
+    if (e & kCountBit) ring_commit(r, e >> 24, len, L.tok);
+  } else {
+    L.cnt += e & kCountBit;
+  }
+  if (EMIT || !MONO) L.tok = (e & kEmitBit) ? p : L.tok;
+  L.st = e & kRowMask;
+  if (!MONO && (e & kAccBit)) {
     L.lacc = p + 1;
     L.lrow = L.st;
   }
 }
 
+template <bool EMIT>
+__device__ __forceinline__ void put(LaneState &L, Ring &r, uint32_t kind, uint32_t end) {
+  if (EMIT) ring_put(r, kind, end - L.tok, L.tok);
+  else ++L.cnt;
+}
+
 // Non-monotone automata: the walk reached FAIL (a dead end after a non-accepting
 // state).  Longest match takes the last accepting position of the current token if
 // there is one: emit it and re-scan from there, byte by byte, up to `upto`; with no
-// accepting position since the token start the scan halts there (SINK).
+// accepting position since the token start the scan halts there (SINK).  The guard on
+// fail != sink keeps the loop finite should a monotone table ever reach it.
 template <bool EMIT>
-__device__ void recover(LaneState &L, Out &o, const Tables &tb, const uint8_t *in, uint32_t upto) {
-  // Only instantiated for non-monotone automata, whose FAIL row differs from SINK; the
-  // guard keeps the loop finite even if a monotone table ever reached here.
+__device__ __forceinline__ void recover(LaneState &L, Ring &r, const Tables &tb, const uint8_t *in, uint32_t upto) {
   while (L.st == tb.fail && tb.fail != tb.sink) {
     if (L.lacc > L.tok) {
-      const uint32_t r = L.lrow >> 8;
-      if (tb.info[r] & kInfoCount) put<EMIT>(L, o, tb.kind[r], L.lacc);
+      const uint32_t row = L.lrow >> kRowShift;
+      if (tb.info[row] & kInfoCount) put<EMIT>(L, r, tb.kind[row], L.lacc);
       L.tok = L.lacc;
       L.st = 0;
       for (uint32_t p = L.tok; p < upto; ++p) {
-        step<EMIT, false>(L, o, tb, in[p], p);
+        step<EMIT, false>(L, r, tb, in[p], p);
         if (L.st == tb.fail) break;
       }
     } else {
@@ -254,17 +380,17 @@ __device__ void recover(LaneState &L, Out &o, const Tables &tb, const uint8_t *i
 // End of the slice: an accepting state emits its token; a non-accepting one halts
 // (monotone) or falls back (non-monotone).  Returns true if the slice halted.
 template <bool EMIT, bool MONO>
-__device__ bool finish(LaneState &L, Out &o, const Tables &tb, const uint8_t *in, uint32_t end) {
+__device__ __forceinline__ bool finish(LaneState &L, Ring &r, const Tables &tb, const uint8_t *in, uint32_t end) {
   for (;;) {
     if (!MONO && L.st == tb.fail) {
-      recover<EMIT>(L, o, tb, in, end);
+      recover<EMIT>(L, r, tb, in, end);
       continue;
     }
     if (L.st == 0) return false;
     if (L.st == tb.sink) return true;
-    const uint32_t r = L.st >> 8;
-    if (tb.info[r] & kInfoAcc) {
-      if (tb.info[r] & kInfoCount) put<EMIT>(L, o, tb.kind[r], end);
+    const uint32_t row = L.st >> kRowShift;
+    if (tb.info[row] & kInfoAcc) {
+      if (tb.info[row] & kInfoCount) put<EMIT>(L, r, tb.kind[row], end);
       L.tok = end;
       L.st = 0;
       return false;
@@ -294,54 +420,117 @@ __device__ __forceinline__ uint32_t byte_of(const uint4 &v, int k) {
   return (w >> (8 * (k & 3))) & 0xFFu;
 }
 
+// A full 16-byte block, unmasked.  FAST: the lane uses the packed ring and writes no
+// offsets (see Ring), so the emit steps need no branch.
+template <bool EMIT, bool MONO, bool FAST>
+__device__ __forceinline__ void block16(LaneState &L, Ring &r, const Tables &tb, const uint4 &v, uint32_t blk) {
+  if (!EMIT && MONO) {
+    // count walk of a monotone automaton: the COUNT bits of the 16 steps are shifted
+    // into m (bit 0 of each entry lands in bit 31) and popcounted once.
+    uint32_t m = 0, st = L.st;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const uint32_t e = entry(tb, st, byte_of(v, k));
+      st = e & kRowMask;
+      m = __builtin_amdgcn_alignbit(e, m, 1);
+    }
+    L.st = st;
+    L.cnt += __builtin_popcount(m);
+    return;
+  }
+  if (EMIT && MONO && FAST) {
+    {
+      // packed emit walk: no branch per byte; chunks are split off after 8 and 16 bytes
+      uint32_t st = L.st, tok = L.tok, o = r.o;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        const uint32_t p = blk + k;
+        const uint32_t e = entry(tb, st, byte_of(v, k));
+        ring_at(r, o & (kSlots - 1)) = pack_word(e, p - tok);
+        o += e & kCountBit;
+        tok = (e & kEmitBit) ? p : tok;
+        st = e & kRowMask;
+        if (k == 7 || k == 15) {
+          r.o = o;
+          ring_maybe_split(r);
+        }
+      }
+      L.st = st;
+      L.tok = tok;
+      return;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 16; ++k) step<EMIT, MONO>(L, r, tb, byte_of(v, k), blk + k);
+}
+
 // Walks the slice [s, e) of in[0, n); returns true if it halted (error inside).
-template <bool EMIT, bool MONO>
-__device__ bool walk(LaneState &L, Out &o, const Tables &tb, const uint8_t *in, uint32_t n, uint32_t s,
+// Input is read in whole 128-byte lines (eight 16-byte loads issued together and
+// consumed from registers), so each cache line is fetched once and used at once
+// instead of staying half-read in L2 while thousands of other lanes stream past it.
+// The slice's unaligned head and tail go through 16-byte blocks, masked per byte at
+// the slice ends.
+template <bool EMIT, bool MONO, bool FAST>
+__device__ __forceinline__ bool walk(LaneState &L, Ring &r, const Tables &tb, const uint8_t *in, uint32_t n, uint32_t s,
                      uint32_t e) {
   L.st = 0;
   L.tok = s;
   L.lacc = s;
   L.lrow = 0;
   if (s >= e) return false;
-  // 16-byte blocks aligned on the absolute address; the first and last blocks of the
-  // slice are processed with a per-byte mask.
   const int64_t mis = (int64_t)(reinterpret_cast<uintptr_t>(in + s) & 15);
-  int64_t blk = (int64_t)s - mis;
-  {
-    const uint4 v = load_block(in, blk, n);
+  int64_t b0 = (int64_t)s - mis;
+  {  // first (masked) block
+    const uint4 v = load_block(in, b0, n);
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
-      const int64_t p = blk + k;
-      if (p >= (int64_t)s && p < (int64_t)e) step<EMIT, MONO>(L, o, tb, byte_of(v, k), (uint32_t)p);
+      const int64_t p = b0 + k;
+      if (p >= (int64_t)s && p < (int64_t)e) step<EMIT, MONO>(L, r, tb, byte_of(v, k), (uint32_t)p);
     }
+    b0 += 16;
+    if (!MONO && L.st == tb.fail) recover<EMIT>(L, r, tb, in, (uint32_t)min<int64_t>(b0, e));
+  }
+  if (b0 >= (int64_t)e) return finish<EMIT, MONO>(L, r, tb, in, e);
+  uint32_t blk = (uint32_t)b0;  // > s and 16-aligned in memory from here on
+  // Lines of kBlocks blocks: whole 128-byte lines for the count walk and the packed
+  // emit walk, single blocks for the generic emit walk.
+  constexpr int kBlocks = EMIT ? (FAST && MONO ? 8 : 1) : 8;
+  // full blocks up to a line boundary
+  while (blk + 16 <= e && (reinterpret_cast<uintptr_t>(in + blk) & (16 * kBlocks - 1))) {
+    const uint4 v = *reinterpret_cast<const uint4 *>(in + blk);
+    block16<EMIT, MONO, FAST>(L, r, tb, v, blk);
     blk += 16;
-    if (!MONO && L.st == tb.fail) recover<EMIT>(L, o, tb, in, (uint32_t)min<int64_t>(blk, e));
+    if (!MONO && L.st == tb.fail) recover<EMIT>(L, r, tb, in, blk);
   }
-  if (blk + 16 <= (int64_t)e) {
-    uint4 v = *reinterpret_cast<const uint4 *>(in + blk);
-    for (;;) {
-      const int64_t nb = blk + 16;
-      const bool more = nb + 16 <= (int64_t)e;
-      uint4 nv = v;
-      if (more) nv = *reinterpret_cast<const uint4 *>(in + nb);  // prefetch the next block
+  while (blk + 16 * kBlocks <= e) {
+    uint4 v[kBlocks];
+    const uint4 *src = reinterpret_cast<const uint4 *>(in + blk);
 #pragma unroll
-      for (int k = 0; k < 16; ++k) step<EMIT, MONO>(L, o, tb, byte_of(v, k), (uint32_t)(blk + k));
-      if (!MONO && L.st == tb.fail) recover<EMIT>(L, o, tb, in, (uint32_t)nb);
-      blk = nb;
-      if (!more) break;
-      v = nv;
+    for (int i = 0; i < kBlocks; ++i) v[i] = src[i];
+#pragma unroll
+    for (int i = 0; i < kBlocks; ++i) {
+      block16<EMIT, MONO, FAST>(L, r, tb, v[i], blk);
+      blk += 16;
+      if (!MONO && L.st == tb.fail) recover<EMIT>(L, r, tb, in, blk);
     }
   }
-  if (blk < (int64_t)e) {
+  // remaining full blocks, then the masked last block
+  while (blk + 16 <= e) {
+    const uint4 v = *reinterpret_cast<const uint4 *>(in + blk);
+    block16<EMIT, MONO, FAST>(L, r, tb, v, blk);
+    blk += 16;
+    if (!MONO && L.st == tb.fail) recover<EMIT>(L, r, tb, in, blk);
+  }
+  if (blk < e) {
     const uint4 v = load_block(in, blk, n);
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
-      const int64_t p = blk + k;
-      if (p < (int64_t)e) step<EMIT, MONO>(L, o, tb, byte_of(v, k), (uint32_t)p);
+      const uint32_t p = blk + k;
+      if (p < e) step<EMIT, MONO>(L, r, tb, byte_of(v, k), p);
     }
-    if (!MONO && L.st == tb.fail) recover<EMIT>(L, o, tb, in, e);
+    if (!MONO && L.st == tb.fail) recover<EMIT>(L, r, tb, in, e);
   }
-  return finish<EMIT, MONO>(L, o, tb, in, e);
+  return finish<EMIT, MONO>(L, r, tb, in, e);
 }
 
 struct WalkArgs {
@@ -349,14 +538,16 @@ struct WalkArgs {
   const uint8_t *rowinfo;
   const uint8_t *rowkind;
   int nrows;
-  uint32_t sink, fail;    // row * 256 (fail == sink for monotone automata)
+  uint32_t sink, fail;    // row byte offsets (fail == sink for monotone automata)
   const uint8_t *in;
   uint32_t n;
-  const uint32_t *cuts;   // pipeline path: lane boundaries
+  uint32_t *cuts;         // lane boundaries (pipeline: planned; fused: recorded starts)
   uint32_t lane_bytes;    // fused path: targets
   uint32_t nlanes;
   const uint8_t *cert;    // fused path: global 256-byte LUT of the useful map
-  uint64_t *counts;
+  CertArg ca;             // fused path: the useful map as SWAR patterns
+  uint32_t *ends;         // fused path: slice ends recorded by the count walk
+  uint32_t *counts;
   uint64_t *blk_sum;
   uint32_t *blk_fail;
   uint32_t *blk_nonempty;
@@ -369,104 +560,169 @@ struct WalkArgs {
   uint64_t cap;
 };
 
-__device__ __forceinline__ void stage_tables(const WalkArgs &a, uint32_t *T, uint8_t *info, uint8_t *kind) {
+// Dynamic LDS layout of the walk kernels (no static LDS, so the table sits at LDS
+// address 0): table | rowinfo | rowkind | lut (256) | reduction scratch | ring.
+struct Lds {
+  uint32_t *T;
+  uint8_t *info, *kind, *lut;
+  uint64_t *red64;   // 16
+  uint32_t *red32;   // 32
+  uint32_t *xchg;    // blockDim (count walk: slice starts)
+  uint8_t *ring;     // blockDim * kRingBytes (emit walk)
+};
+
+__host__ __device__ inline size_t lds_ring_offset(int nrows) {
+  return align16((size_t)nrows * 1024 + 2 * (size_t)nrows + 256) + 16 * 8 + 32 * 4;
+}
+__host__ __device__ inline size_t lds_bytes(int nrows, int block, bool emit) {
+  return lds_ring_offset(nrows) + (size_t)block * (emit ? kRingBytes : 4);
+}
+
+__device__ __forceinline__ Lds carve_lds(int nrows) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  Lds l;
+  l.T = reinterpret_cast<uint32_t *>(smem);
+  l.info = smem + (size_t)nrows * 1024;
+  l.kind = l.info + nrows;
+  l.lut = l.kind + nrows;
+  uint8_t *p = smem + align16((size_t)nrows * 1024 + 2 * (size_t)nrows + 256);
+  l.red64 = reinterpret_cast<uint64_t *>(p);
+  l.red32 = reinterpret_cast<uint32_t *>(p + 16 * 8);
+  l.ring = smem + lds_ring_offset(nrows);
+  l.xchg = reinterpret_cast<uint32_t *>(l.ring);  // the count walk has no ring
+  return l;
+}
+
+__device__ __forceinline__ void stage_tables(const WalkArgs &a, const Lds &l, bool fused) {
   const int words = a.nrows * 256;
   const uint4 *src = reinterpret_cast<const uint4 *>(a.table);
-  uint4 *dst = reinterpret_cast<uint4 *>(T);
+  uint4 *dst = reinterpret_cast<uint4 *>(l.T);
   for (int i = threadIdx.x; i < words / 4; i += blockDim.x) dst[i] = src[i];
   for (int i = threadIdx.x; i < a.nrows; i += blockDim.x) {
-    info[i] = a.rowinfo[i];
-    kind[i] = a.rowkind[i];
+    l.info[i] = a.rowinfo[i];
+    l.kind[i] = a.rowkind[i];
   }
+  if (fused)
+    for (int i = threadIdx.x; i < 256; i += blockDim.x) l.lut[i] = a.cert[i];
   __syncthreads();
 }
 
-// Fused planning: the first certified byte in [x, x + span) (or `none`).
-__device__ uint32_t search_cert(const uint8_t *in, uint32_t n, const uint8_t *lut, uint32_t x, uint32_t span,
-                                uint32_t none) {
+// Certified bytes of a 16-byte block as a 16-bit mask (bit k = byte k).
+__device__ __forceinline__ uint32_t match16(const uint4 &v, const CertArg &ca, const uint8_t *lut) {
+  const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+  uint32_t m = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    uint32_t x = 0;
+    if (ca.np >= 0) {
+      uint32_t z = 0;
+      for (int i = 0; i < ca.np; ++i) z |= zero_bytes(w[q] ^ ca.pat[i]);
+      x = gather4(z);
+    } else {
+      x = match_word_lut(w[q], lut);
+    }
+    m |= x << (4 * q);
+  }
+  return m;
+}
+
+// Fused planning: the first certified byte in [x, x + span) (or `none`), 16 bytes at a
+// time.
+__device__ uint32_t search_cert(const uint8_t *in, uint32_t n, const CertArg &ca, const uint8_t *lut, uint32_t x,
+                                uint32_t span, uint32_t none) {
   const uint32_t end = (uint32_t)min<uint64_t>((uint64_t)x + span, n);
   int64_t blk = (int64_t)x - (int64_t)(reinterpret_cast<uintptr_t>(in + x) & 15);
   for (; blk < (int64_t)end; blk += 16) {
-    const uint4 v = load_block(in, blk, n);
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      const int64_t p = blk + k;
-      if (p >= (int64_t)x && p < (int64_t)end && lut[byte_of(v, k)]) return (uint32_t)p;
-    }
+    uint32_t m = match16(load_block(in, blk, n), ca, lut);
+    if (blk < (int64_t)x) m &= ~0u << (uint32_t)((int64_t)x - blk);       // bytes before x
+    if (blk + 16 > (int64_t)end) m &= (1u << (uint32_t)(end - blk)) - 1;  // bytes at or after end
+    if (m) return (uint32_t)blk + (__ffs(m) - 1);
   }
   return none;
 }
 
 // Lane j's slice.  Pipeline: [cuts[j], cuts[j+1]).  Fused: [c(j l), c((j+1) l)) with c(x)
-// = first certified byte at or after x; the start search is bounded by one lane length
-// (no certified byte there means the slice is empty, because then c(j l) = c((j+1) l)).
+// = first certified byte at or after x.  The start search is bounded by one lane length
+// (no certified byte there means the slice is empty, because then c(j l) = c((j+1) l));
+// the end is the next lane's start when that lane found one, which the lanes of a
+// workgroup exchange through LDS, and a search of its own otherwise.  Every lane of the
+// workgroup must call this (it holds a barrier).
 template <bool FUSED>
-__device__ __forceinline__ void lane_slice(const WalkArgs &a, uint32_t j, const uint8_t *lut, uint32_t &s,
-                                           uint32_t &e) {
+__device__ __forceinline__ void lane_slice(const WalkArgs &a, uint32_t j, const uint8_t *lut, uint32_t *xchg,
+                                           uint32_t &s, uint32_t &e) {
   if (!FUSED) {
-    s = a.cuts[j];
-    e = a.cuts[j + 1];
+    if (j < a.nlanes) {
+      s = a.cuts[j];
+      e = a.cuts[j + 1];
+    }
     return;
   }
   const uint64_t x = (uint64_t)j * a.lane_bytes, x1 = x + a.lane_bytes;
-  if (j == 0) s = 0;
-  else if (x >= a.n) s = a.n;
-  else s = search_cert(a.in, a.n, lut, (uint32_t)x, a.lane_bytes, a.n);
-  if (s >= x1 || s >= a.n) {  // no certified byte in [x, x1): empty slice
-    e = s = (uint32_t)min<uint64_t>(s, a.n);
+  uint32_t start = kNone;  // kNone: no certified byte in [x, x1)
+  if (j < a.nlanes) {
+    if (j == 0) start = 0;
+    else if (x < a.n) start = search_cert(a.in, a.n, a.ca, lut, (uint32_t)x, a.lane_bytes, kNone);
+  }
+  xchg[threadIdx.x] = start;
+  __syncthreads();
+  if (j >= a.nlanes) return;
+  if (start == kNone) {  // empty slice
+    s = e = (uint32_t)min<uint64_t>(x, a.n);
     return;
   }
-  e = (j + 1 == a.nlanes || x1 >= a.n) ? a.n : search_cert(a.in, a.n, lut, (uint32_t)x1, a.n - (uint32_t)x1, a.n);
+  s = start;
+  if (j + 1 == a.nlanes || x1 >= a.n) {
+    e = a.n;
+    return;
+  }
+  const uint32_t next = threadIdx.x + 1 < blockDim.x ? xchg[threadIdx.x + 1] : kNone;
+  e = next != kNone ? next : search_cert(a.in, a.n, a.ca, lut, (uint32_t)x1, a.n - (uint32_t)x1, a.n);
 }
 
 template <bool MONO, bool FUSED>
-__global__ void __launch_bounds__(256) k_count(WalkArgs a) {
-  extern __shared__ __align__(16) uint8_t smem[];
-  uint32_t *T = reinterpret_cast<uint32_t *>(smem);
-  uint8_t *info = smem + (size_t)a.nrows * 1024;
-  uint8_t *kind = info + a.nrows;
-  uint8_t *lut = kind + a.nrows;
-  __shared__ uint64_t wsum[16];
-  __shared__ uint32_t wfail[16], wne[16];
-  if (FUSED)
-    for (int i = threadIdx.x; i < 256; i += blockDim.x) lut[i] = a.cert[i];
-  stage_tables(a, T, info, kind);
-  const Tables tb{T, info, kind, a.sink, a.fail};
+__global__ void __launch_bounds__(1024) k_count(WalkArgs a) {
+  const Lds l = carve_lds(a.nrows);
+  stage_tables(a, l, FUSED);
+  const Tables tb{l.T, l.info, l.kind, a.sink, a.fail};
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-  uint64_t cnt = 0;
-  uint32_t fail = kNone, nonempty = 0;
+  uint32_t cnt = 0, fail = kNone, nonempty = 0;
+  uint32_t s = 0, e = 0;
+  lane_slice<FUSED>(a, j, l.lut, l.xchg, s, e);
   if (j < a.nlanes) {
-    uint32_t s, e;
-    lane_slice<FUSED>(a, j, lut, s, e);
+    if (FUSED) {
+      a.cuts[j] = s;
+      a.ends[j] = e;
+    }
     LaneState L;
     L.cnt = 0;
-    Out o{nullptr, nullptr, nullptr, 0, 0, false};
-    const bool halted = walk<false, MONO>(L, o, tb, a.in, a.n, s, e);
+    Ring r{};
+    const bool halted = walk<false, MONO, false>(L, r, tb, a.in, a.n, s, e);
     cnt = L.cnt;
     a.counts[j] = cnt;
     if (halted) fail = j;
     nonempty = s < e;
   }
   // block reductions: sum, min failing lane, non-empty count
+  uint64_t c64 = cnt;
   for (int d = 32; d; d >>= 1) {
-    cnt += __shfl_xor(cnt, d);
+    c64 += __shfl_xor(c64, d);
     fail = min(fail, (uint32_t)__shfl_xor((int)fail, d));
     nonempty += __shfl_xor(nonempty, d);
   }
   const int wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
   if ((threadIdx.x & 63) == 0) {
-    wsum[wid] = cnt;
-    wfail[wid] = fail;
-    wne[wid] = nonempty;
+    l.red64[wid] = c64;
+    l.red32[wid] = fail;
+    l.red32[16 + wid] = nonempty;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     uint64_t s = 0;
     uint32_t f = kNone, ne = 0;
     for (int w = 0; w < nw; ++w) {
-      s += wsum[w];
-      f = min(f, wfail[w]);
-      ne += wne[w];
+      s += l.red64[w];
+      f = min(f, l.red32[w]);
+      ne += l.red32[16 + w];
     }
     a.blk_sum[blockIdx.x] = s;
     a.blk_fail[blockIdx.x] = f;
@@ -478,7 +734,7 @@ __global__ void __launch_bounds__(256) k_count(WalkArgs a) {
 // output length, status.
 __global__ void __launch_bounds__(1024) k_scan(uint64_t *__restrict__ blk_sum, const uint32_t *__restrict__ blk_fail,
                                                const uint32_t *__restrict__ blk_nonempty, uint32_t nblocks,
-                                               uint32_t block, const uint64_t *__restrict__ counts,
+                                               uint32_t block, const uint32_t *__restrict__ counts,
                                                uint32_t *__restrict__ meta, ResultDev *__restrict__ res, uint64_t cap,
                                                uint32_t n) {
   __shared__ uint64_t part[1024];
@@ -534,44 +790,46 @@ __global__ void __launch_bounds__(1024) k_scan(uint64_t *__restrict__ blk_sum, c
 }
 
 template <bool MONO, bool FUSED>
-__global__ void __launch_bounds__(256) k_emit(WalkArgs a) {
-  extern __shared__ __align__(16) uint8_t smem[];
-  uint32_t *T = reinterpret_cast<uint32_t *>(smem);
-  uint8_t *info = smem + (size_t)a.nrows * 1024;
-  uint8_t *kind = info + a.nrows;
-  uint8_t *lut = kind + a.nrows;
-  __shared__ uint64_t wpre[16];
+__global__ void __launch_bounds__(1024) k_emit(WalkArgs a) {
   const uint32_t first = a.meta[0];
   const uint32_t j0 = blockIdx.x * blockDim.x;
   if (j0 > first) return;  // the whole block lies after the first halted lane
-  if (FUSED)
-    for (int i = threadIdx.x; i < 256; i += blockDim.x) lut[i] = a.cert[i];
-  stage_tables(a, T, info, kind);
-  const Tables tb{T, info, kind, a.sink, a.fail};
+  const Lds l = carve_lds(a.nrows);
+  stage_tables(a, l, FUSED);
+  const Tables tb{l.T, l.info, l.kind, a.sink, a.fail};
   const uint32_t j = j0 + threadIdx.x;
   // exclusive prefix of this block's lane counts
-  uint64_t c = j < a.nlanes ? a.counts[j] : 0;
+  const uint64_t c = j < a.nlanes ? a.counts[j] : 0;
   uint64_t incl = c;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   for (int d = 1; d < 64; d <<= 1) {
     uint64_t v = __shfl_up(incl, d);
     if (lane >= d) incl += v;
   }
-  if (lane == 63) wpre[wid] = incl;
+  if (lane == 63) l.red64[wid] = incl;
   __syncthreads();
-  uint64_t base = a.blk_sum[blockIdx.x];
-  for (int w = 0; w < wid; ++w) base += wpre[w];
-  const uint64_t off = base + incl - c;
+  uint64_t off = a.blk_sum[blockIdx.x];
+  for (int w = 0; w < wid; ++w) off += l.red64[w];
+  off += incl - c;
   if (j >= a.nlanes || j > first) return;
-  uint32_t s, e;
-  lane_slice<FUSED>(a, j, lut, s, e);
-  const bool write = a.res->status == 0;
-  Out o{a.kinds, a.lens, a.offs, off, off + c, write};
+  const uint32_t s = a.cuts[j], e = FUSED ? a.ends[j] : a.cuts[j + 1];
+  Ring r;
+  r.w = reinterpret_cast<uint32_t *>(l.ring) + threadIdx.x;
+  r.stride = blockDim.x;
+  r.kinds = a.kinds;
+  r.lens = a.lens;
+  r.offs = a.offs;
+  r.o = (uint32_t)off;
+  r.fl = (uint32_t)off & ~(uint32_t)(kChunk - 1);
+  r.first = (uint32_t)off;
+  r.write = a.res->status == 0;
+  r.direct = e - s >= (1u << 24);
   LaneState L;
   L.cnt = 0;
-  walk<true, MONO>(L, o, tb, a.in, a.n, s, e);
+  if (!r.direct && !r.offs) walk<true, MONO, true>(L, r, tb, a.in, a.n, s, e);
+  else walk<true, MONO, false>(L, r, tb, a.in, a.n, s, e);
+  ring_flush_tail(r);
   if (j == first) a.res->error_offset = L.tok;  // the halt offset: start of the failed token
-  (void)nw;
 }
 
 }  // namespace
@@ -582,33 +840,38 @@ static size_t carve_layout(uint32_t n, uint32_t lane_bytes, uint32_t block, int 
   const uint32_t nblocks = (nlanes + block - 1) / block;
   const uint32_t nwords = (n + 63) / 64;
   const uint32_t ntiles = (n + kTile - 1) / kTile;
+  const uint32_t ngroups = (ntiles + kTilesPerBlock - 1) / kTilesPerBlock;
   size_t at = 0;
   offs[0] = at;
   at += align256(pipeline ? (size_t)(nwords ? nwords : 1) * 8 : 0);
   offs[1] = at;
   at += align256(pipeline ? (size_t)(ntiles + 1) * 8 : 0);
   offs[2] = at;
-  at += align256((size_t)(nlanes + 1) * 4);
+  at += align256(pipeline ? (size_t)(ngroups + 1) * 8 : 0);
   offs[3] = at;
-  at += align256((size_t)nlanes * 8);
+  at += align256((size_t)(nlanes + 1) * 4);
   offs[4] = at;
-  at += align256((size_t)nblocks * 8);
+  at += align256((size_t)nlanes * 4);
+  offs[9] = at;  // slice ends (fused path)
+  at += align256((size_t)nlanes * 4);
   offs[5] = at;
-  at += align256((size_t)nblocks * 4);
+  at += align256((size_t)nblocks * 8);
   offs[6] = at;
   at += align256((size_t)nblocks * 4);
   offs[7] = at;
+  at += align256((size_t)nblocks * 4);
+  offs[8] = at;
   at += align256(16);
   return at;
 }
 
 size_t workspace_bytes(uint32_t n, uint32_t lane_bytes, uint32_t block, int pipeline) {
-  size_t offs[8];
+  size_t offs[10];
   return carve_layout(n, lane_bytes, block, pipeline, offs);
 }
 
 bool carve(void *ws, size_t ws_bytes, uint32_t n, uint32_t lane_bytes, uint32_t block, int pipeline, Plan &p) {
-  size_t offs[8];
+  size_t offs[10];
   const size_t need = carve_layout(n, lane_bytes, block, pipeline, offs);
   if (ws_bytes < need || !ws) return false;
   uint8_t *b = static_cast<uint8_t *>(ws);
@@ -620,14 +883,18 @@ bool carve(void *ws, size_t ws_bytes, uint32_t n, uint32_t lane_bytes, uint32_t 
   p.ntiles = (n + kTile - 1) / kTile;
   p.bitmap = pipeline ? reinterpret_cast<uint64_t *>(b + offs[0]) : nullptr;
   p.tile_next = pipeline ? reinterpret_cast<uint64_t *>(b + offs[1]) : nullptr;
-  p.cuts = reinterpret_cast<uint32_t *>(b + offs[2]);
-  p.counts = reinterpret_cast<uint64_t *>(b + offs[3]);
-  p.blk_sum = reinterpret_cast<uint64_t *>(b + offs[4]);
-  p.blk_fail = reinterpret_cast<uint32_t *>(b + offs[5]);
-  p.blk_nonempty = reinterpret_cast<uint32_t *>(b + offs[6]);
-  p.meta = reinterpret_cast<uint32_t *>(b + offs[7]);
+  p.tile_group = pipeline ? reinterpret_cast<uint64_t *>(b + offs[2]) : nullptr;
+  p.cuts = reinterpret_cast<uint32_t *>(b + offs[3]);
+  p.counts = reinterpret_cast<uint32_t *>(b + offs[4]);
+  p.ends = reinterpret_cast<uint32_t *>(b + offs[9]);
+  p.blk_sum = reinterpret_cast<uint64_t *>(b + offs[5]);
+  p.blk_fail = reinterpret_cast<uint32_t *>(b + offs[6]);
+  p.blk_nonempty = reinterpret_cast<uint32_t *>(b + offs[7]);
+  p.meta = reinterpret_cast<uint32_t *>(b + offs[8]);
   return true;
 }
+
+size_t walk_lds_bytes(int nrows, uint32_t block, bool emit) { return lds_bytes(nrows, (int)block, emit); }
 
 static CertArg cert_arg(const CertMap &cm) {
   CertArg ca{};
@@ -648,15 +915,17 @@ hipError_t launch_bitmap(const uint8_t *in, uint32_t n, const CertMap &cm, uint6
   return hipGetLastError();
 }
 
-static WalkArgs walk_args(const DevTable &t, const uint8_t *in, const Plan &p, uint8_t *kinds, uint32_t *lens,
-                          uint64_t *offs, uint64_t cap, ResultDev *res, const uint8_t *cert_lut) {
+static WalkArgs walk_args(const DevTable &t, const CertMap &cm, const uint8_t *in, const Plan &p, uint8_t *kinds,
+                          uint32_t *lens, uint64_t *offs, uint64_t cap, ResultDev *res, const uint8_t *cert_lut) {
   WalkArgs a{};
+  a.ca = cert_arg(cm);
+  a.ends = p.ends;
   a.table = t.table;
   a.rowinfo = t.rowinfo;
   a.rowkind = t.rowkind;
   a.nrows = t.nrows;
-  a.sink = (uint32_t)t.row_sink * 256u;
-  a.fail = t.row_fail >= 0 ? (uint32_t)t.row_fail * 256u : a.sink;
+  a.sink = ((uint32_t)t.row_sink << kRowShift) | (((uint32_t)t.row_sink & 31u) << 2);
+  a.fail = t.row_fail >= 0 ? ((uint32_t)t.row_fail << kRowShift) | (((uint32_t)t.row_fail & 31u) << 2) : a.sink;
   a.in = in;
   a.n = p.n;
   a.cuts = p.cuts;
@@ -683,13 +952,11 @@ static inline void mark(hipEvent_t const *ev, int i, hipStream_t s) {
 template <bool FUSED>
 static hipError_t count_scan_emit(const DevTable &t, const WalkArgs &a, const Plan &p, uint64_t cap,
                                   ResultDev *res, hipStream_t s, hipEvent_t const *ev) {
-  const size_t smem = (size_t)t.nrows * 1024 + 2 * (size_t)t.nrows + 256;
+  const size_t smem_c = lds_bytes(t.nrows, (int)p.block, false);
+  const size_t smem_e = lds_bytes(t.nrows, (int)p.block, true);
   mark(ev, 1, s);
-  if (t.monotone) {
-    k_count<true, FUSED><<<p.nblocks, p.block, smem, s>>>(a);
-  } else {
-    k_count<false, FUSED><<<p.nblocks, p.block, smem, s>>>(a);
-  }
+  if (t.monotone) k_count<true, FUSED><<<p.nblocks, p.block, smem_c, s>>>(a);
+  else k_count<false, FUSED><<<p.nblocks, p.block, smem_c, s>>>(a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   mark(ev, 2, s);
@@ -698,11 +965,8 @@ static hipError_t count_scan_emit(const DevTable &t, const WalkArgs &a, const Pl
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   mark(ev, 3, s);
-  if (t.monotone) {
-    k_emit<true, FUSED><<<p.nblocks, p.block, smem, s>>>(a);
-  } else {
-    k_emit<false, FUSED><<<p.nblocks, p.block, smem, s>>>(a);
-  }
+  if (t.monotone) k_emit<true, FUSED><<<p.nblocks, p.block, smem_e, s>>>(a);
+  else k_emit<false, FUSED><<<p.nblocks, p.block, smem_e, s>>>(a);
   e = hipGetLastError();
   mark(ev, 4, s);
   return e;
@@ -718,17 +982,23 @@ hipError_t run_pipeline(const DevTable &t, const CertMap &cm, const uint8_t *in,
   if (one && p.nlanes != 1) return hipErrorInvalidValue;  // the host plans one lane then
   if (!one) {
     const uint32_t nwords = (p.n + 63) / 64;
+    const uint32_t ngroups = (p.ntiles + kTilesPerBlock - 1) / kTilesPerBlock;
+    if (ngroups > 1024) return hipErrorInvalidValue;
     k_bitmap<<<(nwords + 255) / 256, 256, 0, s>>>(in, p.n, cert_arg(cm), p.bitmap, p.tile_next);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_tiles<<<1, 1024, 0, s>>>(p.tile_next, p.ntiles);
+    k_tiles_blocks<<<ngroups, kTilesPerBlock, 0, s>>>(p.tile_next, p.ntiles, p.tile_group);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_tiles_top<<<1, 1024, 0, s>>>(p.tile_group, ngroups);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  k_plan<<<(p.nlanes + 1 + 255) / 256, 256, 0, s>>>(p.bitmap, p.tile_next, p.n, p.lane_bytes, p.nlanes, p.cuts);
+  k_plan<<<(p.nlanes + 1 + 255) / 256, 256, 0, s>>>(p.bitmap, p.tile_next, p.tile_group, p.n, p.lane_bytes,
+                                                    p.nlanes, p.cuts);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const WalkArgs a = walk_args(t, in, p, kinds, lens, offs, cap, res, nullptr);
+  const WalkArgs a = walk_args(t, cm, in, p, kinds, lens, offs, cap, res, nullptr);
   return count_scan_emit<false>(t, a, p, cap, res, s, ev);
 }
 
@@ -738,7 +1008,7 @@ hipError_t run_fused(const DevTable &t, const CertMap &cm, const uint8_t *cert_l
   mark(ev, 0, s);
   const bool one = serial || p.nlanes == 1 || cm.nbytes == 0;
   if (one && p.nlanes != 1) return hipErrorInvalidValue;
-  const WalkArgs a = walk_args(t, in, p, kinds, lens, offs, cap, res, cert_lut);
+  const WalkArgs a = walk_args(t, cm, in, p, kinds, lens, offs, cap, res, cert_lut);
   return count_scan_emit<true>(t, a, p, cap, res, s, ev);
 }
 

@@ -96,9 +96,11 @@ DevCopy *device_copy(lex_dfa *d) {
   return c;
 }
 
+uint32_t default_block(int nrows);
+
 int finish_compile(lex_dfa *d, lex_dfa **out, char *err, size_t errlen) {
   const lexc::Compiled &c = d->c;
-  if ((size_t)c.nrows * 1024 + 2 * (size_t)c.nrows + 256 > 160 * 1024) {
+  if (default_block(c.nrows) == 0) {
     set_err(err, errlen, "automaton too large for the LDS-resident table (" + std::to_string(c.nrows) + " rows)");
     release(d);
     return LEX_ELIMIT;
@@ -137,11 +139,18 @@ struct Resolved {
 };
 
 uint32_t default_lane_bytes(uint64_t n) {
-  // Aim for about 256k lanes (one per lane slot of a full MI355X at 1024 threads per
-  // CU), between 64 B and 4 KiB.
+  // Aim for about 512k lanes (2048 resident lanes on each of 256 CUs), between 64 B
+  // and 4 KiB.
   uint64_t l = 64;
-  while (l < 4096 && n / l > (256u << 10)) l <<= 1;
+  while (l < 4096 && n / l > (512u << 10)) l <<= 1;
   return (uint32_t)l;
+}
+
+// Largest workgroup (1024, 512 or 256 lanes) whose emit-walk LDS fits the CU's 160 KiB.
+uint32_t default_block(int nrows) {
+  for (uint32_t b = 1024; b >= 256; b >>= 1)
+    if (lexk::walk_lds_bytes(nrows, b, true) <= 160 * 1024) return b;
+  return 0;
 }
 
 int resolve(const lex_dfa *d, uint64_t n, int mode, const lex_run_opts *o, Resolved &r) {
@@ -150,9 +159,10 @@ int resolve(const lex_dfa *d, uint64_t n, int mode, const lex_run_opts *o, Resol
   r.serial = (mode & 2) != 0 || d->cm[r.table].nbytes == 0;
   r.path = o && o->path ? o->path : 1;
   if (r.path != 1 && r.path != 2) return LEX_EINVAL;
-  r.block = o && o->block_threads ? (uint32_t)o->block_threads : 256u;
+  r.block = o && o->block_threads ? (uint32_t)o->block_threads : default_block(d->c.nrows);
   if (o && o->reserved) return LEX_EINVAL;
-  if (r.block != 256u) return LEX_EINVAL;  // kernels are compiled for 256-thread groups
+  if (r.block != 256u && r.block != 512u && r.block != 1024u) return LEX_EINVAL;
+  if (lexk::walk_lds_bytes(d->c.nrows, r.block, true) > 160 * 1024) return LEX_ELIMIT;
   uint32_t lb = o && o->lane_bytes ? o->lane_bytes : default_lane_bytes(n);
   if (lb < 16 || (lb & 15)) return LEX_EINVAL;
   if (o && o->chunk_bytes) {
@@ -268,6 +278,8 @@ int lex_run(const lex_dfa *d, const uint8_t *d_bytes, uint64_t n, int mode, uint
             const lex_run_opts *opts, void *stream) {
   if (!d || !d_result || (!d_bytes && n) || !d_ws) return LEX_EINVAL;
   if (cap && (!d_kinds || !d_lens)) return LEX_EINVAL;
+  // outputs leave the kernels in 16-byte chunks
+  if ((reinterpret_cast<uintptr_t>(d_kinds) | reinterpret_cast<uintptr_t>(d_lens)) & 15) return LEX_EINVAL;
   if (n > 0xFFFFFFF0ull) return LEX_ELIMIT;
   Resolved r;
   int rc = resolve(d, n, mode, opts, r);

@@ -1,11 +1,13 @@
 """A slow host model of the GPU lane walker, run on the library's packed tables.
 
 It restates, in plain Python, what one lane does with the packed table of include/lex.h's
-library (entry bits: next row * 256 in 0..19, kind in 20..27, ACC 28, EMIT 30, COUNT 31;
-row 0 = token start, SINK after the DFA rows, FAIL after SINK for non-monotone automata).
+library (entry bits: COUNT 0, EMIT 1, row swizzle (row & 31) in 2..6, ACC 7, next-row byte
+offset (row * 1024) in 10..23, kind in 24..31; row r keeps byte b's entry at index
+r * 256 + (b ^ (r & 31)); row 0 = token start, SINK after the DFA rows, FAIL after SINK for
+non-monotone automata).
 Tests use it to check the *tables* against the oracle on the CPU before any kernel runs.
 """
-NEXT, ACC, EMIT, COUNT = 0xFFFFF, 1 << 28, 1 << 30, 1 << 31
+ROWMASK, ACC, EMIT, COUNT = 0x00FFFC00, 1 << 7, 1 << 1, 1 << 0
 INFO_ACC, INFO_COUNT = 0x80, 0x40
 
 
@@ -13,6 +15,7 @@ class Model:
     def __init__(self, lexer, mode):
         self.T, self.info, self.kind = lexer.tables(mode & 1)
         inf = lexer.info()
+        # row states are kept as row index * 256, the index of the row's first entry
         self.sink = (1 + inf["nstates"]) * 256
         self.mono = bool(inf["monotone"])
         self.fail = self.sink if self.mono else (2 + inf["nstates"]) * 256
@@ -41,12 +44,12 @@ class Model:
 
         def step(b, p):
             nonlocal st, tok, lacc, lrow
-            x = int(T[st + b])
+            x = int(T[st + (b ^ ((st >> 8) & 31))])
             if x & EMIT:
                 if x & COUNT:
-                    out.append(((x >> 20) & 0xFF, p - tok, tok))
+                    out.append(((x >> 24) & 0xFF, p - tok, tok))
                 tok = p
-            st = x & NEXT
+            st = (x & ROWMASK) >> 2
             if x & ACC:
                 lacc, lrow = p + 1, st
 

@@ -4,6 +4,8 @@ import ctypes as C
 import os
 import re
 
+import numpy as np
+
 import pytest
 
 import paper_2608_03473_amd as P
@@ -51,4 +53,6 @@ def test_info_and_tables():
     t, ri, rk = lx.tables(1)
     assert t.size == info["nrows"] * 256 and ri.size == info["nrows"]
     # every next-row field points at a row of the table
-    assert int(((t & 0xFFFFF) >> 8).max()) < info["nrows"]
+    assert int(((t & 0x00FFFC00) >> 10).max()) < info["nrows"]
+    # the swizzle field matches the next row
+    assert np.array_equal((t >> 2) & 31, ((t >> 10) & 0x3FFF) & 31)
