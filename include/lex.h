@@ -126,17 +126,24 @@ int lex_tables(const lex_dfa *dfa, int mode, uint32_t *table, size_t table_entri
  * chunk_bytes; 0 = chosen from n).  path: 0 = default, 1 = the five-step pipeline
  * (bitmap, plan, count walk, scan, emit walk), 2 = fused (each lane finds its own cut,
  * no bitmap).  block_threads: threads per walk workgroup, 256, 512 or 1024 (0 = the
- * largest whose LDS fits).  events: optional array of LEX_NPHASES + 1 hipEvent_t (passed as void*,
- * created by the caller) recorded on the scan's stream at the phase boundaries: [0] start,
- * [1] after planning (steps a, b), [2] after the count walk (c), [3] after the scan (d),
- * [4] after the emit walk (e). */
+ * largest whose LDS fits).  emit: 0 = default, 1 = lane emit only.  By default a scan
+ * whose automaton is monotone (no live edge from an accepting to a non-accepting state),
+ * counts every token end in its mode (exact mode, or no discarded kind) and has at most
+ * 256 rows uses the windowed emit: the count walk records checkpoints every 64 bytes
+ * and the emit walk runs one thread per 64-byte sub-slice; a scan with a halted slice or
+ * a slice of 2^24 bytes or more falls back to the lane emit (one thread per slice) on the
+ * device.  Both write the same outputs.  events: optional array of LEX_NPHASES + 1
+ * hipEvent_t (passed as void*, created by the caller) recorded on the scan's stream at
+ * the phase boundaries: [0] start, [1] after planning (steps a, b), [2] after the count
+ * walk (c), [3] after the scan (d), [4] after the emit walk (e). */
 enum { LEX_NPHASES = 4 };
+enum { LEX_EMIT_DEFAULT = 0, LEX_EMIT_LANE = 1 };
 typedef struct {
   uint64_t chunk_bytes;
   uint32_t lane_bytes;
   int32_t path;
   int32_t block_threads;
-  int32_t reserved;
+  int32_t emit;
   void *const *events;
 } lex_run_opts;
 

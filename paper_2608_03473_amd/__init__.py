@@ -8,9 +8,9 @@ on first use and its absence is an error (there is no CPU fallback).
     lx = Lexer.compile(defs)                 # defs: [(pattern, priority, discard), ...]
     kinds, lens, err = lx.run(u8_cuda_tensor, mode=LEX_MODE_EXACT)
 """
-from .abi import (LEX_EDEVICE, LEX_EINVAL, LEX_ELIMIT, LEX_ENOMEM, LEX_EOVERFLOW, LEX_ESYNTAX,  # noqa: F401
-                  LEX_MODE_DISCARD, LEX_MODE_EXACT, LEX_MODE_SERIAL, LEX_OK, LexError, RunOpts,
-                  lib, lib_path)
+from .abi import (LEX_EDEVICE, LEX_EINVAL, LEX_ELIMIT, LEX_EMIT_DEFAULT, LEX_EMIT_LANE,  # noqa: F401
+                  LEX_ENOMEM, LEX_EOVERFLOW, LEX_ESYNTAX, LEX_MODE_DISCARD, LEX_MODE_EXACT,
+                  LEX_MODE_SERIAL, LEX_OK, LexError, RunOpts, lib, lib_path)
 from .lexer import Lexer, RunResult  # noqa: F401
 
 __all__ = ["Lexer", "RunResult", "RunOpts", "LexError", "lib", "lib_path",

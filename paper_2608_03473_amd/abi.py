@@ -35,11 +35,12 @@ class Info(C.Structure):
 
 
 LEX_NPHASES = 4
+LEX_EMIT_DEFAULT, LEX_EMIT_LANE = 0, 1
 
 
 class RunOpts(C.Structure):
     _fields_ = [("chunk_bytes", C.c_uint64), ("lane_bytes", C.c_uint32), ("path", C.c_int32),
-                ("block_threads", C.c_int32), ("reserved", C.c_int32), ("events", C.c_void_p)]
+                ("block_threads", C.c_int32), ("emit", C.c_int32), ("events", C.c_void_p)]
 
 
 _lib = None

@@ -17,6 +17,7 @@ struct DevTable {
   int row_sink;            // index
   int row_fail;            // index, -1 if the automaton is monotone
   int monotone;
+  int all_counted;         // every token end of this mode is counted (no discarded kind)
 };
 
 // The useful certificate map of the scan's mode, in a form the bitmap kernel uses.
@@ -43,15 +44,33 @@ struct Plan {
   uint64_t *blk_sum;       // nblocks
   uint32_t *blk_fail;      // nblocks: first halted lane of the block or ~0u
   uint32_t *blk_nonempty;  // nblocks
-  uint32_t *meta;          // [0] = first halted lane or ~0u
+  uint32_t *blk_big;       // nblocks: a slice of 2^24 bytes or more (no checkpoints)
+  uint32_t *meta;          // [0] = first halted lane or ~0u, [1] = checkpoints unusable
+  uint32_t *lane_pre;      // nlanes: exclusive prefix of counts inside the workgroup
+  // Windowed emit (monotone automata whose token ends are all counted): the count walk
+  // records its state at every 64-byte-aligned address strictly inside a slice; the emit
+  // walk then runs one thread per 64-byte window of the input.
+  int windowed;
+  uint2 *ck;               // checkpoints: kslots * nlanes, window-in-lane-major
+  uint2 *ck_over;          // window-indexed checkpoints beyond a lane's kslots
+  uint32_t kslots;
+  int32_t *lnz;            // nlanes: last non-empty lane at or before it in its workgroup, or -1
+  int32_t *blk_lnz;        // nblocks: last non-empty lane of the earlier workgroups, or -1
 };
 
-size_t workspace_bytes(uint32_t n, uint32_t lane_bytes, uint32_t block, int pipeline);
+constexpr uint32_t kWin = 64;  // window of the windowed emit
+// Windows of n bytes at any alignment of the input, plus one.
+uint32_t windows_max(uint32_t n);
+uint32_t ck_slots(uint32_t lane_bytes);
+
+size_t workspace_bytes(uint32_t n, uint32_t lane_bytes, uint32_t block, int pipeline, int windowed);
 // Dynamic LDS of a walk workgroup: the table, its row info and, for the emit walk, a
 // 96-byte token ring per lane.
 size_t walk_lds_bytes(int nrows, uint32_t block, bool emit);
+// Dynamic LDS of a windowed-emit workgroup (the table and four wave stages).
+size_t window_lds_bytes(int nrows);
 bool carve(void *ws, size_t ws_bytes, uint32_t n, uint32_t lane_bytes, uint32_t block, int pipeline,
-           Plan &p);
+           int windowed, Plan &p);
 
 struct ResultDev {  // mirrors lex_result
   uint64_t ntokens;

@@ -29,6 +29,8 @@
 // swizzle, so the next entry's LDS address is (e & kRowMask) ^ (b << 2).
 // Row 0 is the token start, SINK absorbs after a halt, FAIL (non-monotone automata only)
 // marks a dead end that falls back to the last accepting position.
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace lexk {
@@ -340,7 +342,7 @@ __device__ __forceinline__ void step(LaneState &L, Ring &r, const Tables &tb, ui
   } else {
     L.cnt += e & kCountBit;
   }
-  if (EMIT || !MONO) L.tok = (e & kEmitBit) ? p : L.tok;
+  L.tok = (e & kEmitBit) ? p : L.tok;
   L.st = e & kRowMask;
   if (!MONO && (e & kAccBit)) {
     L.lacc = p + 1;
@@ -420,6 +422,36 @@ __device__ __forceinline__ uint32_t byte_of(const uint4 &v, int k) {
   return (w >> (8 * (k & 3))) & 0xFFu;
 }
 
+// Checkpoints of the count walk for the windowed emit.  Windows are the kWin-aligned
+// stretches of the input's address space: window i starts at position i * kWin - mis0
+// (mis0 = the input's address modulo kWin).  When a lane's walk reaches a window start
+// strictly inside its slice it records, for that window, the row it is in before reading
+// the byte, the tokens it has counted so far and the start of the token in progress.
+//
+// Storage: a window whose start lies k = (start - j l) / kWin windows into lane j's nominal
+// range [j l, (j + 1) l) keeps its checkpoint at main[k * nlanes + j] when k < kslots, so
+// the lanes of a wave, which cross their k-th windows at about the same step, fill whole
+// cache lines together; the rare windows further out (a slice running far past its lane)
+// go to over[window index].
+struct CkSink {
+  uint2 *main;      // null: off
+  uint2 *over;
+  uint32_t nlanes, kslots, j, jl;  // jl = j * lane_bytes
+  uint32_t mis0;
+  uintptr_t base;   // address of the input
+};
+
+__device__ __forceinline__ void ck_record(const CkSink &c, const LaneState &L, uint32_t blk) {
+  const uint2 v = make_uint2(((L.st >> kRowShift) << 24) | L.cnt, L.tok);
+  const uint32_t k = (blk - c.jl) / kWin;
+  if (k < c.kslots) c.main[(size_t)k * c.nlanes + c.j] = v;
+  else c.over[(blk + c.mis0) / kWin] = v;
+}
+
+__device__ __forceinline__ void ck_maybe(const CkSink &c, const LaneState &L, uint32_t blk) {
+  if (c.main && ((c.base + blk) & (kWin - 1)) == 0) ck_record(c, L, blk);
+}
+
 // A full 16-byte block, unmasked.  FAST: the lane uses the packed ring and writes no
 // offsets (see Ring), so the emit steps need no branch.
 template <bool EMIT, bool MONO, bool FAST>
@@ -436,6 +468,9 @@ __device__ __forceinline__ void block16(LaneState &L, Ring &r, const Tables &tb,
     }
     L.st = st;
     L.cnt += __builtin_popcount(m);
+    // start of the token in progress: the last step whose token ended (bit 16 + k
+    // holds step k); only read by checkpoints, whose tables count every token end
+    L.tok = m ? blk + 15 - __clz(m) : L.tok;
     return;
   }
   if (EMIT && MONO && FAST) {
@@ -470,9 +505,9 @@ __device__ __forceinline__ void block16(LaneState &L, Ring &r, const Tables &tb,
 // instead of staying half-read in L2 while thousands of other lanes stream past it.
 // The slice's unaligned head and tail go through 16-byte blocks, masked per byte at
 // the slice ends.
-template <bool EMIT, bool MONO, bool FAST>
+template <bool EMIT, bool MONO, bool FAST, bool CK = false>
 __device__ __forceinline__ bool walk(LaneState &L, Ring &r, const Tables &tb, const uint8_t *in, uint32_t n, uint32_t s,
-                     uint32_t e) {
+                     uint32_t e, const CkSink &ck = CkSink{}) {
   L.st = 0;
   L.tok = s;
   L.lacc = s;
@@ -498,6 +533,7 @@ __device__ __forceinline__ bool walk(LaneState &L, Ring &r, const Tables &tb, co
   // full blocks up to a line boundary
   while (blk + 16 <= e && (reinterpret_cast<uintptr_t>(in + blk) & (16 * kBlocks - 1))) {
     const uint4 v = *reinterpret_cast<const uint4 *>(in + blk);
+    if (CK) ck_maybe(ck, L, blk);
     block16<EMIT, MONO, FAST>(L, r, tb, v, blk);
     blk += 16;
     if (!MONO && L.st == tb.fail) recover<EMIT>(L, r, tb, in, blk);
@@ -509,6 +545,8 @@ __device__ __forceinline__ bool walk(LaneState &L, Ring &r, const Tables &tb, co
     for (int i = 0; i < kBlocks; ++i) v[i] = src[i];
 #pragma unroll
     for (int i = 0; i < kBlocks; ++i) {
+      // a line starts on a 128-byte boundary, so its blocks 0 and 4 start windows
+      if (CK && ck.main && (i * 16) % kWin == 0) ck_record(ck, L, blk);
       block16<EMIT, MONO, FAST>(L, r, tb, v[i], blk);
       blk += 16;
       if (!MONO && L.st == tb.fail) recover<EMIT>(L, r, tb, in, blk);
@@ -517,11 +555,13 @@ __device__ __forceinline__ bool walk(LaneState &L, Ring &r, const Tables &tb, co
   // remaining full blocks, then the masked last block
   while (blk + 16 <= e) {
     const uint4 v = *reinterpret_cast<const uint4 *>(in + blk);
+    if (CK) ck_maybe(ck, L, blk);
     block16<EMIT, MONO, FAST>(L, r, tb, v, blk);
     blk += 16;
     if (!MONO && L.st == tb.fail) recover<EMIT>(L, r, tb, in, blk);
   }
   if (blk < e) {
+    if (CK) ck_maybe(ck, L, blk);
     const uint4 v = load_block(in, blk, n);
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
@@ -551,6 +591,15 @@ struct WalkArgs {
   uint64_t *blk_sum;
   uint32_t *blk_fail;
   uint32_t *blk_nonempty;
+  uint32_t *blk_big;
+  uint32_t *lane_pre;     // exclusive prefix of counts inside the workgroup
+  uint2 *ck;              // checkpoints (windowed emit), null when not recorded: main part
+  uint2 *ck_over;         // and overflow (see CkSink)
+  uint32_t kslots;
+  int32_t *lnz;           // per lane: last non-empty lane at or before it in its workgroup, or -1
+  int32_t *blk_lnz;       // per workgroup: last non-empty lane (count); before it (after the scan)
+  uint32_t block;         // lanes per count workgroup (lane_pre's groups)
+  int fallback_only;      // lane emit: run only when the windowed emit cannot
   // emit
   const uint32_t *meta;
   ResultDev *res;
@@ -679,13 +728,14 @@ __device__ __forceinline__ void lane_slice(const WalkArgs &a, uint32_t j, const 
   e = next != kNone ? next : search_cert(a.in, a.n, a.ca, lut, (uint32_t)x1, a.n - (uint32_t)x1, a.n);
 }
 
-template <bool MONO, bool FUSED>
+// CK: record checkpoints for the windowed emit (monotone automata only).
+template <bool MONO, bool FUSED, bool CK>
 __global__ void __launch_bounds__(1024) k_count(WalkArgs a) {
   const Lds l = carve_lds(a.nrows);
   stage_tables(a, l, FUSED);
   const Tables tb{l.T, l.info, l.kind, a.sink, a.fail};
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-  uint32_t cnt = 0, fail = kNone, nonempty = 0;
+  uint32_t cnt = 0, fail = kNone, nonempty = 0, big = 0;
   uint32_t s = 0, e = 0;
   lane_slice<FUSED>(a, j, l.lut, l.xchg, s, e);
   if (j < a.nlanes) {
@@ -696,44 +746,88 @@ __global__ void __launch_bounds__(1024) k_count(WalkArgs a) {
     LaneState L;
     L.cnt = 0;
     Ring r{};
-    const bool halted = walk<false, MONO, false>(L, r, tb, a.in, a.n, s, e);
+    bool halted;
+    if (CK) {
+      // checkpoints hold the count in 24 bits: longer slices record none, and the
+      // windowed emit then stands down for the whole scan
+      big = e - s >= (1u << 24);
+      CkSink ck{};
+      ck.base = reinterpret_cast<uintptr_t>(a.in);
+      ck.main = big ? nullptr : a.ck;
+      ck.over = a.ck_over;
+      ck.nlanes = a.nlanes;
+      ck.kslots = a.kslots;
+      ck.j = j;
+      ck.jl = j * a.lane_bytes;
+      ck.mis0 = (uint32_t)(ck.base & (kWin - 1));
+      halted = walk<false, MONO, false, true>(L, r, tb, a.in, a.n, s, e, ck);
+    } else {
+      halted = walk<false, MONO, false>(L, r, tb, a.in, a.n, s, e);
+    }
     cnt = L.cnt;
     a.counts[j] = cnt;
     if (halted) fail = j;
     nonempty = s < e;
   }
-  // block reductions: sum, min failing lane, non-empty count
-  uint64_t c64 = cnt;
+  // block reductions: exclusive prefix and sum of counts, min failing lane, non-empty
+  // count, any long slice
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  uint32_t incl = cnt;
+  int32_t lnz = j < a.nlanes && nonempty ? (int32_t)j : -1;  // last non-empty lane so far
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t v = __shfl_up(incl, d);
+    const int32_t z = __shfl_up(lnz, d);
+    if (lane >= d) {
+      incl += v;
+      lnz = max(lnz, z);
+    }
+  }
   for (int d = 32; d; d >>= 1) {
-    c64 += __shfl_xor(c64, d);
     fail = min(fail, (uint32_t)__shfl_xor((int)fail, d));
     nonempty += __shfl_xor(nonempty, d);
+    big |= __shfl_xor(big, d);
   }
-  const int wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  if ((threadIdx.x & 63) == 0) {
-    l.red64[wid] = c64;
+  // red64[w]: the wave's count sum (low half) and last non-empty lane (high half)
+  if (lane == 63) l.red64[wid] = ((uint64_t)(uint32_t)lnz << 32) | incl;
+  if (lane == 0) {
     l.red32[wid] = fail;
-    l.red32[16 + wid] = nonempty;
+    l.red32[16 + wid] = nonempty | (big << 31);
   }
   __syncthreads();
+  uint32_t pre = 0;
+  for (int w = 0; w < wid; ++w) {
+    pre += (uint32_t)l.red64[w];
+    lnz = max(lnz, (int32_t)(l.red64[w] >> 32));
+  }
+  if (j < a.nlanes) {
+    a.lane_pre[j] = pre + incl - cnt;
+    a.lnz[j] = lnz;
+  }
   if (threadIdx.x == 0) {
-    uint64_t s = 0;
-    uint32_t f = kNone, ne = 0;
+    uint64_t sum = 0;
+    uint32_t f = kNone, ne = 0, bg = 0;
     for (int w = 0; w < nw; ++w) {
-      s += l.red64[w];
+      sum += (uint32_t)l.red64[w];
       f = min(f, l.red32[w]);
-      ne += l.red32[16 + w];
+      ne += l.red32[16 + w] & 0x7FFFFFFFu;
+      bg |= l.red32[16 + w] >> 31;
     }
-    a.blk_sum[blockIdx.x] = s;
+    a.blk_sum[blockIdx.x] = sum;
     a.blk_fail[blockIdx.x] = f;
     a.blk_nonempty[blockIdx.x] = ne;
+    a.blk_big[blockIdx.x] = bg;
+    int32_t z = -1;
+    for (int w = 0; w < nw; ++w) z = max(z, (int32_t)(l.red64[w] >> 32));
+    a.blk_lnz[blockIdx.x] = z;
   }
 }
 
 // (d) One workgroup: exclusive scan of block sums (in place), first halted lane,
 // output length, status.
 __global__ void __launch_bounds__(1024) k_scan(uint64_t *__restrict__ blk_sum, const uint32_t *__restrict__ blk_fail,
-                                               const uint32_t *__restrict__ blk_nonempty, uint32_t nblocks,
+                                               const uint32_t *__restrict__ blk_nonempty,
+                                               const uint32_t *__restrict__ blk_big,
+                                               int32_t *__restrict__ blk_lnz, uint32_t nblocks,
                                                uint32_t block, const uint32_t *__restrict__ counts,
                                                uint32_t *__restrict__ meta, ResultDev *__restrict__ res, uint64_t cap,
                                                uint32_t n) {
@@ -742,32 +836,47 @@ __global__ void __launch_bounds__(1024) k_scan(uint64_t *__restrict__ blk_sum, c
   const uint32_t tid = threadIdx.x, nt = blockDim.x;
   const uint32_t per = (nblocks + nt - 1) / nt;
   const uint32_t lo = min(nblocks, tid * per), hi = min(nblocks, lo + per);
+  __shared__ uint32_t any_big;
+  if (tid == 0) any_big = 0;
+  __syncthreads();
+  __shared__ int32_t pz[1024];
   uint64_t s = 0;
-  uint32_t f = kNone, ne = 0;
+  uint32_t f = kNone, ne = 0, bg = 0;
+  int32_t z = -1;
   for (uint32_t i = lo; i < hi; ++i) {
     s += blk_sum[i];
     f = min(f, blk_fail[i]);
     ne += blk_nonempty[i];
+    bg |= blk_big[i];
+    z = max(z, blk_lnz[i]);
   }
+  if (bg) atomicOr(&any_big, 1u);
   part[tid] = s;
   pf[tid] = f;
   pn[tid] = ne;
+  pz[tid] = z;
   __syncthreads();
-  for (uint32_t d = 1; d < nt; d <<= 1) {  // inclusive prefix sums, min, sum
+  for (uint32_t d = 1; d < nt; d <<= 1) {  // inclusive prefix sums, min, sum, max
     uint64_t v = tid >= d ? part[tid - d] : 0;
     uint32_t vf = tid >= d ? pf[tid - d] : kNone;
     uint32_t vn = tid >= d ? pn[tid - d] : 0;
+    int32_t vz = tid >= d ? pz[tid - d] : -1;
     __syncthreads();
     part[tid] += v;
     pf[tid] = min(pf[tid], vf);
     pn[tid] += vn;
+    pz[tid] = max(pz[tid], vz);
     __syncthreads();
   }
   uint64_t run = tid ? part[tid - 1] : 0;
+  int32_t zrun = tid ? pz[tid - 1] : -1;
   for (uint32_t i = lo; i < hi; ++i) {
     const uint64_t x = blk_sum[i];
     blk_sum[i] = run;
     run += x;
+    const int32_t y = blk_lnz[i];
+    blk_lnz[i] = zrun;  // last non-empty lane of the earlier workgroups
+    zrun = max(zrun, y);
   }
   __syncthreads();
   if (tid == 0) {
@@ -782,6 +891,7 @@ __global__ void __launch_bounds__(1024) k_scan(uint64_t *__restrict__ blk_sum, c
       ntok = blk_sum[b] + pre + counts[first];
     }
     meta[0] = first;
+    meta[1] = any_big;
     res->ntokens = ntok;
     res->error_offset = n;  // replaced by the halted lane in the emit pass
     res->status = ntok > cap ? -4 : 0;
@@ -792,26 +902,16 @@ __global__ void __launch_bounds__(1024) k_scan(uint64_t *__restrict__ blk_sum, c
 template <bool MONO, bool FUSED>
 __global__ void __launch_bounds__(1024) k_emit(WalkArgs a) {
   const uint32_t first = a.meta[0];
+  // beside the windowed emit, this kernel takes the scans that one cannot
+  if (a.fallback_only && first == kNone && a.meta[1] == 0) return;
   const uint32_t j0 = blockIdx.x * blockDim.x;
   if (j0 > first) return;  // the whole block lies after the first halted lane
   const Lds l = carve_lds(a.nrows);
   stage_tables(a, l, FUSED);
   const Tables tb{l.T, l.info, l.kind, a.sink, a.fail};
   const uint32_t j = j0 + threadIdx.x;
-  // exclusive prefix of this block's lane counts
-  const uint64_t c = j < a.nlanes ? a.counts[j] : 0;
-  uint64_t incl = c;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int d = 1; d < 64; d <<= 1) {
-    uint64_t v = __shfl_up(incl, d);
-    if (lane >= d) incl += v;
-  }
-  if (lane == 63) l.red64[wid] = incl;
-  __syncthreads();
-  uint64_t off = a.blk_sum[blockIdx.x];
-  for (int w = 0; w < wid; ++w) off += l.red64[w];
-  off += incl - c;
   if (j >= a.nlanes || j > first) return;
+  const uint64_t off = a.blk_sum[blockIdx.x] + a.lane_pre[j];
   const uint32_t s = a.cuts[j], e = FUSED ? a.ends[j] : a.cuts[j + 1];
   Ring r;
   r.w = reinterpret_cast<uint32_t *>(l.ring) + threadIdx.x;
@@ -832,10 +932,300 @@ __global__ void __launch_bounds__(1024) k_emit(WalkArgs a) {
   if (j == first) a.res->error_offset = L.tok;  // the halt offset: start of the failed token
 }
 
+
+// ---------------------------------------------------------- (e) windowed emit
+// For a monotone automaton whose token ends are all counted, and a scan with no halted
+// slice, the emit needs no lane-long walks.  Every lane starts at a certified byte, where
+// the serial lexer also starts a token (Theorem 1), so the lanes' states, counts and token
+// starts agree with the serial lexer's everywhere; the count walk left them at every
+// window start.  One thread walks one kWin-byte window from its checkpoint, straight
+// through any lane start inside it (for a monotone automaton the serial step there is
+// the token end the lane walk took at its slice end), and finishes the input's last token.
+//
+// Windows in order, 64 to a wave: a wave's windows are a contiguous 4 KiB of input and own
+// a contiguous range of output slots.  The wave stages that range in LDS as words
+// (end - P) << 8 | kind, P being the start of the range's first token, and writes it out
+// with 16-byte stores; lengths are the differences of consecutive ends.  A range longer
+// than the stage (less its 64 spill words), or spanning 2^24 bytes or more, is written
+// token by token instead.
+//
+// A window's output offset comes from the lane that owns its first byte: lane j0 =
+// start / lane_bytes when that lane is not empty and starts at or before it, otherwise
+// the last non-empty lane before j0 (slices tile the input, and a non-empty lane j starts
+// inside [j l, (j + 1) l)).
+constexpr int kWinWaves = 4;             // waves per workgroup
+constexpr uint32_t kStageWords = 1280;   // staged words per wave
+
+__host__ __device__ inline size_t win_lds_bytes(int nrows) {
+  return lds_ring_offset(nrows) + (size_t)kWinWaves * kStageWords * 4;
+}
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ uint32_t row_state(uint32_t row) { return (row << kRowShift) | ((row & 31u) << 2); }
+
+// First-round loads for the window starting at position ws (owner candidates, checkpoint).
+struct WinR1 {
+  uint32_t ws, j0, s0, e0;
+  int32_t lz, bz;  // last non-empty lane at or before j0 - 1: in its workgroup; before it
+};
+
+template <bool FUSED>
+__device__ __forceinline__ WinR1 win_r1(const WalkArgs &a, uint32_t i, uint32_t mis0, uint32_t nwin) {
+  WinR1 r{};
+  if (i >= nwin) return r;
+  r.ws = i ? i * kWin - mis0 : 0;
+  r.j0 = min(r.ws / a.lane_bytes, a.nlanes - 1);
+  r.s0 = a.cuts[r.j0];
+  r.e0 = FUSED ? a.ends[r.j0] : a.cuts[r.j0 + 1];
+  r.lz = r.j0 ? a.lnz[r.j0 - 1] : -1;
+  r.bz = r.j0 ? a.blk_lnz[(r.j0 - 1) / a.block] : -1;
+  return r;
+}
+
+// Second round: the owner's output offset.  Window nwin (past the end) gives ntok.
+struct WinMeta {
+  uint32_t st, tok;
+  uint64_t out;
+  bool fresh;  // a lane starts at the window's first byte
+};
+
+__device__ __forceinline__ WinMeta win_meta(const WalkArgs &a, const WinR1 &r, uint32_t i, uint32_t nwin,
+                                            uint64_t ntok) {
+  WinMeta m{0, 0, ntok, false};
+  if (i >= nwin) return m;
+  const bool here = r.s0 < r.e0 && r.s0 <= r.ws;
+  const uint32_t owner = here ? r.j0 : (uint32_t)(r.lz >= 0 ? r.lz : r.bz);
+  const uint64_t base = a.blk_sum[owner / a.block] + a.lane_pre[owner];
+  const bool fresh = here && r.s0 == r.ws;
+  uint2 c = make_uint2(0, 0);
+  if (!fresh) {
+    const uint32_t k = (r.ws - owner * a.lane_bytes) / kWin;
+    c = k < a.kslots ? a.ck[(size_t)k * a.nlanes + owner] : a.ck_over[i];
+  }
+  if (fresh) {  // the owner starts here: a fresh token
+    m.st = 0;
+    m.tok = r.ws;
+    m.out = base;
+    m.fresh = true;
+  } else {
+    m.st = row_state(c.x >> 24);
+    m.tok = c.y;
+    m.out = base + (c.x & 0xFFFFFFu);
+  }
+  return m;
+}
+
+// Output of the staged and the direct walk.
+struct WinOut {
+  uint32_t g, d;       // staged: spill slot address, distance to the next slot
+  uint32_t base;       // staged: P
+  uint32_t tok;        // direct: start of the token in progress
+  uint64_t o, lim;     // direct: next output slot, end of the thread's range
+};
+
+template <bool STAGED>
+__device__ __forceinline__ void win_step(const Tables &tb, const WalkArgs &a, uint32_t &st, WinOut &w, uint32_t b,
+                                         uint32_t p) {
+  const uint32_t e = entry(tb, st, b);
+  if (STAGED) {
+    const uint32_t c = e & kCountBit;
+    *(__attribute__((address_space(3))) uint32_t *)(size_t)(w.g + c * w.d) =
+        __builtin_amdgcn_perm(e, p - w.base, 0x02010007u);
+    w.d += c << 2;
+  } else {
+    if ((e & kCountBit) && w.o < w.lim) {
+      a.kinds[w.o] = (uint8_t)(e >> 24);
+      a.lens[w.o] = p - w.tok;
+      if (a.offs) a.offs[w.o] = w.tok;
+      ++w.o;
+    }
+    w.tok = (e & kEmitBit) ? p : w.tok;
+  }
+  st = e & kRowMask;
+}
+
+// The window's 64 bytes at position wp (its kWin-aligned start, possibly before 0).
+struct Win64 {
+  uint4 v[4];
+};
+
+__device__ __forceinline__ Win64 win_load(const uint8_t *in, int64_t wp, uint32_t n) {
+  Win64 d;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t p = wp + 16 * q;
+    d.v[q] = (p >= 0 && p + 16 <= (int64_t)n) ? *reinterpret_cast<const uint4 *>(in + p) : load_block(in, p, n);
+  }
+  return d;
+}
+
+// Walks the window [wp, wp + 64) ∩ [0, n).  EDGE: some positions may lie outside.
+template <bool STAGED, bool EDGE>
+__device__ __forceinline__ void win_walk(const Tables &tb, const WalkArgs &a, const Win64 &d, int64_t wp,
+                                         uint32_t n, uint32_t &st, WinOut &w) {
+  const uint32_t p0 = (uint32_t)wp;  // positions p0 + k modulo 2^32; only those in [0, n) are walked
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int64_t p = wp + 16 * q + k;
+      if (!EDGE || (p >= 0 && p < (int64_t)n)) win_step<STAGED>(tb, a, st, w, byte_of(d.v[q], k), p0 + 16 * q + k);
+    }
+  }
+}
+
+template <bool FUSED>
+__global__ void __launch_bounds__(256) k_emit_win(WalkArgs a) {
+  if (a.meta[0] != kNone || a.meta[1] != 0 || a.res->status != 0 || a.n == 0) return;
+  const Lds l = carve_lds(a.nrows);
+  stage_tables(a, l, false);
+  const Tables tb{l.T, l.info, l.kind, a.sink, a.fail};
+  const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  uint32_t *stage = reinterpret_cast<uint32_t *>(l.ring) + wid * kStageWords;
+  const uint32_t stage_addr = (uint32_t)(size_t)(__attribute__((address_space(3))) uint32_t *)stage;
+  const uintptr_t base = reinterpret_cast<uintptr_t>(a.in);
+  const uint32_t mis0 = (uint32_t)(base & (kWin - 1));
+  const uint32_t nwin = (uint32_t)(((uint64_t)a.n + mis0 + kWin - 1) / kWin);
+  const uint32_t ntiles = (nwin + 63) / 64;
+  const uint64_t ntok = a.res->ntokens;  // every store below stays under it
+  // Each XCD (workgroups are dealt to the 8 XCDs in turn) takes a contiguous run of
+  // tiles, so neighbouring windows share its L2.
+  const uint32_t nxcd = gridDim.x >= 8 ? 8 : 1;
+  const uint32_t xcd = blockIdx.x % nxcd, per_xcd_wg = gridDim.x / nxcd;
+  const uint32_t xcd_tiles = (ntiles + nxcd - 1) / nxcd;
+  const uint32_t t_lo = xcd * xcd_tiles, t_hi = min(ntiles, t_lo + xcd_tiles);
+  const uint32_t tstep = per_xcd_wg * kWinWaves;
+  uint32_t tile = t_lo + (blockIdx.x / nxcd) * kWinWaves + wid;
+  if (blockIdx.x / nxcd >= per_xcd_wg) tile = t_hi;  // workgroups beyond a multiple of 8
+  // software pipeline: metadata and bytes of the next tile load while this one walks
+  WinR1 r1a = win_r1<FUSED>(a, tile * 64 + lane, mis0, nwin), r1b = win_r1<FUSED>(a, tile * 64 + lane + 1, mis0, nwin);
+  Win64 dat = win_load(a.in, (int64_t)tile * 64 * kWin + (int64_t)lane * kWin - mis0, a.n);
+  WinMeta ma = win_meta(a, r1a, tile * 64 + lane, nwin, ntok), mb = win_meta(a, r1b, tile * 64 + lane + 1, nwin, ntok);
+  for (; tile < t_hi; tile += tstep) {
+    const uint32_t i = tile * 64 + lane;
+    const uint32_t next = tile + tstep;
+    const bool has_next = next < t_hi;
+    WinR1 n1a{}, n1b{};
+    Win64 ndat{};
+    if (has_next) {
+      n1a = win_r1<FUSED>(a, next * 64 + lane, mis0, nwin);
+      n1b = win_r1<FUSED>(a, next * 64 + lane + 1, mis0, nwin);
+      ndat = win_load(a.in, (int64_t)next * 64 * kWin + (int64_t)lane * kWin - mis0, a.n);
+    }
+    const bool valid = i < nwin;
+    const uint64_t out = ma.out;
+    const uint64_t cnt = valid ? mb.out - ma.out : 0;
+    const uint64_t o_first = __shfl(out, 0);
+    const uint64_t o_end = __shfl(valid ? mb.out : 0, (int)min<uint32_t>(63, nwin - 1 - tile * 64));
+    const uint32_t P = __shfl(ma.tok, 0);  // start of the token in progress at the tile's start
+    const uint64_t total = o_end - o_first;
+    const uint32_t pad = (uint32_t)(o_first & 3);
+    const int64_t wp = (int64_t)i * kWin - mis0;
+    const uint32_t span_end = (uint32_t)min<int64_t>((int64_t)(tile + 1) * 64 * kWin - mis0, a.n);
+    const bool staged = o_first <= o_end && o_end <= ntok && total + pad + 3 <= kStageWords - 64 &&
+                        span_end - P < (1u << 24);
+    const bool edge = tile == 0 || tile + 1 == ntiles;  // a window reaching outside [0, n)
+    uint32_t st = ma.st;
+    WinOut w;
+    if (staged) {
+      w.g = stage_addr + 4 * (kStageWords - 64 + lane);  // spill slots: the stage's last 64 words
+      w.d = stage_addr + 4 * (pad + (uint32_t)(out - o_first)) - w.g;
+      w.base = P;
+      if (valid) {
+        if (edge) win_walk<true, true>(tb, a, dat, wp, a.n, st, w);
+        else win_walk<true, false>(tb, a, dat, wp, a.n, st, w);
+      }
+    } else {
+      w.tok = ma.tok;
+      w.o = out;
+      w.lim = min(out + cnt, ntok);
+      if (valid) {
+        if (edge) win_walk<false, true>(tb, a, dat, wp, a.n, st, w);
+        else win_walk<false, false>(tb, a, dat, wp, a.n, st, w);
+      }
+    }
+    // The input's end, or a lane starting at the next window's first byte: the token in
+    // progress ends here, as the lane walk's slice end made it (the next window starts
+    // afresh and does not see it).
+    if (valid && (i + 1 == nwin || mb.fresh) && st != 0) {
+      const uint32_t end = i + 1 == nwin ? a.n : (i + 1) * kWin - mis0;
+      const uint32_t row = st >> kRowShift;
+      if ((tb.info[row] & kInfoAcc) && (tb.info[row] & kInfoCount)) {
+        if (staged) {
+          *(__attribute__((address_space(3))) uint32_t *)(size_t)(w.g + w.d) =
+              (uint32_t)tb.kind[row] | ((end - P) << 8);
+        } else if (w.o < w.lim) {
+          a.kinds[w.o] = tb.kind[row];
+          a.lens[w.o] = end - w.tok;
+          if (a.offs) a.offs[w.o] = w.tok;
+        }
+      }
+    }
+    // the next tile's owner offsets, before this tile's stores
+    WinMeta nma{}, nmb{};
+    if (has_next) {
+      nma = win_meta(a, n1a, next * 64 + lane, nwin, ntok);
+      nmb = win_meta(a, n1b, next * 64 + lane + 1, nwin, ntok);
+    }
+    if (staged) {
+      wave_sync();
+      // write the range out: slot q holds output o_first - pad + q
+      const uint64_t o0 = o_first - pad;
+      for (uint32_t q = lane * 4; q < pad + total; q += 256) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(stage + q);
+        const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
+        uint32_t prev = q > pad ? stage[q - 1] >> 8 : 0;
+        uint32_t len[4], kd = 0;
+        uint64_t st4[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const uint32_t endp = wv[k] >> 8;
+          const uint32_t pv = q + k > pad ? prev : 0;
+          len[k] = endp - pv;
+          st4[k] = (uint64_t)P + pv;
+          kd |= (wv[k] & 0xFFu) << (8 * k);
+          prev = endp;
+        }
+        if (q >= pad && q + 4 <= pad + total) {
+          *reinterpret_cast<uint4 *>(a.lens + o0 + q) = make_uint4(len[0], len[1], len[2], len[3]);
+          *reinterpret_cast<uint32_t *>(a.kinds + o0 + q) = kd;
+          if (a.offs) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) a.offs[o0 + q + k] = st4[k];
+          }
+        } else {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            if (q + k >= pad && q + k < pad + total) {
+              a.lens[o0 + q + k] = len[k];
+              a.kinds[o0 + q + k] = (uint8_t)(kd >> (8 * k));
+              if (a.offs) a.offs[o0 + q + k] = st4[k];
+            }
+          }
+        }
+      }
+      wave_sync();
+    }
+    ma = nma;
+    mb = nmb;
+    dat = ndat;
+  }
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ host side
-static size_t carve_layout(uint32_t n, uint32_t lane_bytes, uint32_t block, int pipeline, size_t *offs) {
+uint32_t windows_max(uint32_t n) { return (uint32_t)(((uint64_t)n + 2 * kWin - 1) / kWin); }
+// A lane's nominal range plus four windows of slack (slices usually end within a line
+// of their lane's end).
+uint32_t ck_slots(uint32_t lane_bytes) { return lane_bytes / kWin + 4; }
+
+static size_t carve_layout(uint32_t n, uint32_t lane_bytes, uint32_t block, int pipeline, int windowed,
+                           size_t *offs) {
   const uint32_t nlanes = n ? (n + lane_bytes - 1) / lane_bytes : 1;
   const uint32_t nblocks = (nlanes + block - 1) / block;
   const uint32_t nwords = (n + 63) / 64;
@@ -862,17 +1252,28 @@ static size_t carve_layout(uint32_t n, uint32_t lane_bytes, uint32_t block, int 
   at += align256((size_t)nblocks * 4);
   offs[8] = at;
   at += align256(16);
+  offs[10] = at;  // per-block long-slice flags
+  at += align256((size_t)nblocks * 4);
+  offs[11] = at;  // in-block count prefixes
+  at += align256((size_t)nlanes * 4);
+  offs[12] = at;  // checkpoints: main part, then overflow (one spare window for any alignment)
+  if (windowed) at += align256((size_t)ck_slots(lane_bytes) * nlanes * 8) + align256((size_t)windows_max(n) * 8);
+  offs[13] = at;  // per lane: last non-empty lane in the workgroup so far
+  at += align256((size_t)nlanes * 4);
+  offs[14] = at;  // per workgroup: last non-empty lane
+  at += align256((size_t)nblocks * 4);
   return at;
 }
 
-size_t workspace_bytes(uint32_t n, uint32_t lane_bytes, uint32_t block, int pipeline) {
-  size_t offs[10];
-  return carve_layout(n, lane_bytes, block, pipeline, offs);
+size_t workspace_bytes(uint32_t n, uint32_t lane_bytes, uint32_t block, int pipeline, int windowed) {
+  size_t offs[15];
+  return carve_layout(n, lane_bytes, block, pipeline, windowed, offs);
 }
 
-bool carve(void *ws, size_t ws_bytes, uint32_t n, uint32_t lane_bytes, uint32_t block, int pipeline, Plan &p) {
-  size_t offs[10];
-  const size_t need = carve_layout(n, lane_bytes, block, pipeline, offs);
+bool carve(void *ws, size_t ws_bytes, uint32_t n, uint32_t lane_bytes, uint32_t block, int pipeline, int windowed,
+           Plan &p) {
+  size_t offs[15];
+  const size_t need = carve_layout(n, lane_bytes, block, pipeline, windowed, offs);
   if (ws_bytes < need || !ws) return false;
   uint8_t *b = static_cast<uint8_t *>(ws);
   p.n = n;
@@ -891,10 +1292,19 @@ bool carve(void *ws, size_t ws_bytes, uint32_t n, uint32_t lane_bytes, uint32_t 
   p.blk_fail = reinterpret_cast<uint32_t *>(b + offs[6]);
   p.blk_nonempty = reinterpret_cast<uint32_t *>(b + offs[7]);
   p.meta = reinterpret_cast<uint32_t *>(b + offs[8]);
+  p.blk_big = reinterpret_cast<uint32_t *>(b + offs[10]);
+  p.lane_pre = reinterpret_cast<uint32_t *>(b + offs[11]);
+  p.windowed = windowed;
+  p.kslots = ck_slots(lane_bytes);
+  p.ck = windowed ? reinterpret_cast<uint2 *>(b + offs[12]) : nullptr;
+  p.ck_over = windowed ? reinterpret_cast<uint2 *>(b + offs[12] + align256((size_t)p.kslots * p.nlanes * 8)) : nullptr;
+  p.lnz = reinterpret_cast<int32_t *>(b + offs[13]);
+  p.blk_lnz = reinterpret_cast<int32_t *>(b + offs[14]);
   return true;
 }
 
 size_t walk_lds_bytes(int nrows, uint32_t block, bool emit) { return lds_bytes(nrows, (int)block, emit); }
+size_t window_lds_bytes(int nrows) { return win_lds_bytes(nrows); }
 
 static CertArg cert_arg(const CertMap &cm) {
   CertArg ca{};
@@ -936,6 +1346,14 @@ static WalkArgs walk_args(const DevTable &t, const CertMap &cm, const uint8_t *i
   a.blk_sum = p.blk_sum;
   a.blk_fail = p.blk_fail;
   a.blk_nonempty = p.blk_nonempty;
+  a.blk_big = p.blk_big;
+  a.lane_pre = p.lane_pre;
+  a.ck = p.ck;
+  a.ck_over = p.ck_over;
+  a.kslots = p.kslots;
+  a.lnz = p.lnz;
+  a.blk_lnz = p.blk_lnz;
+  a.block = p.block;
   a.meta = p.meta;
   a.res = res;
   a.kinds = kinds;
@@ -949,22 +1367,43 @@ static inline void mark(hipEvent_t const *ev, int i, hipStream_t s) {
   if (ev && ev[i]) (void)hipEventRecord(ev[i], s);
 }
 
+// Workgroups of the windowed emit: enough to fill every CU as far as its LDS allows,
+// looping over the wave tiles.
+static uint32_t win_grid(int nrows, uint32_t ntiles) {
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  const uint32_t per_cu = std::min<uint32_t>(8, (uint32_t)(160 * 1024 / win_lds_bytes(nrows)));
+  const uint32_t want = (ntiles + kWinWaves - 1) / kWinWaves;
+  const uint32_t g = std::max<uint32_t>(1, std::min<uint32_t>(want, (uint32_t)cus * std::max<uint32_t>(per_cu, 1)));
+  return g >= 8 ? g & ~7u : g;  // whole rounds of the 8 XCDs
+}
+
 template <bool FUSED>
-static hipError_t count_scan_emit(const DevTable &t, const WalkArgs &a, const Plan &p, uint64_t cap,
+static hipError_t count_scan_emit(const DevTable &t, const WalkArgs &a0, const Plan &p, uint64_t cap,
                                   ResultDev *res, hipStream_t s, hipEvent_t const *ev) {
+  WalkArgs a = a0;
   const size_t smem_c = lds_bytes(t.nrows, (int)p.block, false);
   const size_t smem_e = lds_bytes(t.nrows, (int)p.block, true);
+  const bool win = p.windowed && t.monotone;
   mark(ev, 1, s);
-  if (t.monotone) k_count<true, FUSED><<<p.nblocks, p.block, smem_c, s>>>(a);
-  else k_count<false, FUSED><<<p.nblocks, p.block, smem_c, s>>>(a);
+  if (win) k_count<true, FUSED, true><<<p.nblocks, p.block, smem_c, s>>>(a);
+  else if (t.monotone) k_count<true, FUSED, false><<<p.nblocks, p.block, smem_c, s>>>(a);
+  else k_count<false, FUSED, false><<<p.nblocks, p.block, smem_c, s>>>(a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   mark(ev, 2, s);
-  k_scan<<<1, 1024, 0, s>>>(p.blk_sum, p.blk_fail, p.blk_nonempty, p.nblocks, p.block, p.counts, p.meta, res, cap,
-                            p.n);
+  k_scan<<<1, 1024, 0, s>>>(p.blk_sum, p.blk_fail, p.blk_nonempty, p.blk_big, p.blk_lnz, p.nblocks, p.block,
+                            p.counts, p.meta, res, cap, p.n);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   mark(ev, 3, s);
+  if (win) {
+    const uint32_t ntiles = (windows_max(p.n) + 63) / 64;
+    k_emit_win<FUSED><<<win_grid(t.nrows, ntiles), kWinWaves * 64, win_lds_bytes(t.nrows), s>>>(a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    a.fallback_only = 1;  // halted scans and long slices
+  }
   if (t.monotone) k_emit<true, FUSED><<<p.nblocks, p.block, smem_e, s>>>(a);
   else k_emit<false, FUSED><<<p.nblocks, p.block, smem_e, s>>>(a);
   e = hipGetLastError();

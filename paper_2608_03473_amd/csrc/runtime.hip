@@ -29,6 +29,7 @@ struct DevCopy {
 struct lex_dfa {
   lexc::Compiled c;
   lexk::CertMap cm[2];
+  bool all_counted[2];  // every token end of the mode is counted (no discarded kind)
   std::vector<uint8_t> lut[2];
   // Tables are uploaded once per device: eagerly by lex_compile when a device is
   // present, otherwise by the first scan on that device.
@@ -106,6 +107,11 @@ int finish_compile(lex_dfa *d, lex_dfa **out, char *err, size_t errlen) {
     return LEX_ELIMIT;
   }
   for (int m = 0; m < 2; ++m) {
+    d->all_counted[m] = true;
+    for (uint32_t e : c.table[m])
+      if ((e & lexc::kEmit) && !(e & lexc::kCount)) d->all_counted[m] = false;
+  }
+  for (int m = 0; m < 2; ++m) {
     const uint8_t *map = m == 0 ? c.exact_useful : c.discard_useful;
     lexk::CertMap &cm = d->cm[m];
     memset(&cm, 0, sizeof cm);
@@ -136,6 +142,7 @@ struct Resolved {
   int path;  // 1 pipeline, 2 fused
   bool serial;
   int table;  // 0 exact, 1 discard
+  bool windowed;
 };
 
 uint32_t default_lane_bytes(uint64_t n) {
@@ -160,7 +167,10 @@ int resolve(const lex_dfa *d, uint64_t n, int mode, const lex_run_opts *o, Resol
   r.path = o && o->path ? o->path : 1;
   if (r.path != 1 && r.path != 2) return LEX_EINVAL;
   r.block = o && o->block_threads ? (uint32_t)o->block_threads : default_block(d->c.nrows);
-  if (o && o->reserved) return LEX_EINVAL;
+  const int emit = o ? o->emit : LEX_EMIT_DEFAULT;
+  if (emit != LEX_EMIT_DEFAULT && emit != LEX_EMIT_LANE) return LEX_EINVAL;
+  r.windowed = emit == LEX_EMIT_DEFAULT && d->c.monotone && d->all_counted[r.table] && d->c.nrows <= 256 &&
+               lexk::window_lds_bytes(d->c.nrows) <= 160 * 1024;
   if (r.block != 256u && r.block != 512u && r.block != 1024u) return LEX_EINVAL;
   if (lexk::walk_lds_bytes(d->c.nrows, r.block, true) > 160 * 1024) return LEX_ELIMIT;
   uint32_t lb = o && o->lane_bytes ? o->lane_bytes : default_lane_bytes(n);
@@ -270,7 +280,7 @@ int lex_tables(const lex_dfa *d, int mode, uint32_t *table, size_t table_entries
 size_t lex_workspace_size(const lex_dfa *d, uint64_t n, int mode, const lex_run_opts *opts) {
   Resolved r;
   if (!d || n > 0xFFFFFFF0ull || resolve(d, n, mode, opts, r) != LEX_OK) return 0;
-  return lexk::workspace_bytes((uint32_t)n, r.lane_bytes, r.block, r.path == 1);
+  return lexk::workspace_bytes((uint32_t)n, r.lane_bytes, r.block, r.path == 1, r.windowed);
 }
 
 int lex_run(const lex_dfa *d, const uint8_t *d_bytes, uint64_t n, int mode, uint8_t *d_kinds, uint32_t *d_lens,
@@ -285,12 +295,13 @@ int lex_run(const lex_dfa *d, const uint8_t *d_bytes, uint64_t n, int mode, uint
   int rc = resolve(d, n, mode, opts, r);
   if (rc != LEX_OK) return rc;
   lexk::Plan p;
-  if (!lexk::carve(d_ws, ws_bytes, (uint32_t)n, r.lane_bytes, r.block, r.path == 1, p)) return LEX_ELIMIT;
+  if (!lexk::carve(d_ws, ws_bytes, (uint32_t)n, r.lane_bytes, r.block, r.path == 1, r.windowed, p))
+    return LEX_ELIMIT;
   const int m = r.table;
   DevCopy *dc = device_copy(const_cast<lex_dfa *>(d));
   if (!dc) return LEX_EDEVICE;
   lexk::DevTable t{dc->d_table[m], dc->d_rowinfo[m], dc->d_rowkind, d->c.nrows, d->c.row_sink, d->c.row_fail,
-                   d->c.monotone ? 1 : 0};
+                   d->c.monotone ? 1 : 0, d->all_counted[m] ? 1 : 0};
   hipStream_t s = static_cast<hipStream_t>(stream);
   auto *res = reinterpret_cast<lexk::ResultDev *>(d_result);
   hipEvent_t const *ev = opts && opts->events ? reinterpret_cast<hipEvent_t const *>(opts->events) : nullptr;

@@ -84,3 +84,171 @@ class Model:
             if halt is not None:
                 return toks, halt
         return toks, len(w)
+
+
+def plan_cuts(w: bytes, cert, lane: int):
+    """Lane boundaries c(j l) (c(0) = 0, c(x) = first certified byte at or after x, or n)."""
+    n = len(w)
+    nl = max(1, -(-n // lane))
+    nxt = [n] * (n + 1)
+    for i in range(n - 1, -1, -1):
+        nxt[i] = i if w[i] in cert else nxt[i + 1]
+    cuts = [0] + [nxt[min(j * lane, n)] for j in range(1, nl)] + [n]
+    return cuts
+
+
+def plan_fused(w: bytes, cert, lane: int):
+    """Slice starts and ends as the fused planner records them: lane j searches [j l, (j+1) l)
+    for a certified byte; without one its slice is empty at min(j l, n); a slice ends at the
+    next lane's start or, when that lane found none, at the first certified byte after it."""
+    n = len(w)
+    nl = max(1, -(-n // lane))
+    first = []
+    for j in range(nl):
+        if j == 0:
+            first.append(0)
+            continue
+        hit = next((p for p in range(j * lane, min((j + 1) * lane, n)) if w[p] in cert), None)
+        first.append(hit)
+    starts, ends = [], []
+    for j in range(nl):
+        if first[j] is None:
+            starts.append(min(j * lane, n))
+            ends.append(min(j * lane, n))
+            continue
+        starts.append(first[j])
+        if j + 1 == nl or (j + 1) * lane >= n:
+            ends.append(n)
+        elif first[j + 1] is not None:
+            ends.append(first[j + 1])
+        else:
+            ends.append(next((p for p in range((j + 1) * lane, n) if w[p] in cert), n))
+    return starts, ends
+
+
+def windowed(model, w: bytes, starts, ends, lane: int, base: int, block: int = 4,
+             stage_words: int = 1280, W: int = 64):
+    """The checkpointed count walk and the windowed emit of the library, restated.
+
+    starts/ends: the lanes' slices (lane j nominally covers [j l, (j+1) l)).  base: the
+    input's address modulo W.  block: lanes per count workgroup.  Returns (kinds, lens, offs),
+    or None when a slice halts (the library then uses the lane emit).  Mirrors the kernels'
+    bookkeeping: window checkpoints, owner lookup through the last-non-empty-lane prefixes,
+    64-window tiles, the staged words (end - P) << 8 | kind with the 4-slot padding, and the
+    direct fallback for ranges longer than the stage.
+    """
+    T, info, kind = model.T, model.info, model.kind
+    n, nl, mis0 = len(w), len(starts), base % W
+    kslots = lane // W + 4
+    counts, nonempty, ck = [0] * nl, [False] * nl, {}
+
+    def ent(st, b):
+        return int(T[st + (b ^ ((st >> 8) & 31))])
+
+    for j in range(nl):
+        s, e = starts[j], ends[j]
+        nonempty[j] = s < e
+        st, cnt, tok = 0, 0, s
+        for p in range(s, e):
+            if p > s and (base + p) % W == 0:
+                # main slots by (window within the lane's nominal range, lane), else overflow
+                k = (p - j * lane) // W
+                ck[(k, j) if k < kslots else ("over", (p + mis0) // W)] = (st >> 8, cnt, tok)
+            x = ent(st, w[p])
+            cnt += x & COUNT
+            if x & EMIT:
+                tok = p
+            st = (x & ROWMASK) >> 2
+        if st != 0:
+            r = st >> 8
+            if st == model.sink or not (info[r] & INFO_ACC):
+                return None  # halted slice
+            if info[r] & INFO_COUNT:
+                cnt += 1
+        counts[j] = cnt
+    nb = -(-nl // block)
+    lane_pre, lnz, blk_sum, blk_lnz = [0] * nl, [-1] * nl, [0] * nb, [-1] * nb
+    run, zrun = 0, -1
+    for b in range(nb):
+        blk_sum[b], blk_lnz[b] = run, zrun
+        acc, z = 0, -1
+        for j in range(b * block, min(nl, (b + 1) * block)):
+            lane_pre[j] = acc
+            acc += counts[j]
+            if nonempty[j]:
+                z = j
+            lnz[j] = z
+        run += acc
+        zrun = max(zrun, z)
+    ntok = run
+    nwin = -(-(n + mis0) // W) if n else 0
+
+    def meta(i):
+        """(row state, token start, output offset, a lane starts here) at window i's start."""
+        if i >= nwin:
+            return 0, 0, ntok, False
+        ws = i * W - mis0 if i else 0
+        j0 = min(ws // lane, nl - 1)
+        here = starts[j0] < ends[j0] and starts[j0] <= ws
+        owner = j0 if here else (lnz[j0 - 1] if lnz[j0 - 1] >= 0 else blk_lnz[(j0 - 1) // block])
+        off = blk_sum[owner // block] + lane_pre[owner]
+        if here and starts[j0] == ws:
+            return 0, ws, off, True
+        k = (ws - owner * lane) // W
+        r, run, tok = ck[(k, owner) if k < kslots else ("over", i)]
+        return r * 256, tok, off + run, False
+
+    kinds, lens, offs = [None] * ntok, [None] * ntok, [None] * ntok
+    for tile in range(-(-nwin // 64)):
+        ids = [tile * 64 + L for L in range(64)]
+        ms = [meta(i) for i in ids]
+        nxt = [meta(i + 1) for i in ids]
+        o_first = ms[0][2]
+        last = min(63, nwin - 1 - tile * 64)
+        o_end = nxt[last][2]
+        P = ms[0][1]
+        total, pad = o_end - o_first, o_first & 3
+        span_end = min((tile + 1) * 64 * W - mis0, n)
+        staged = o_first <= o_end <= ntok and total + pad + 3 <= stage_words - 64 and span_end - P < (1 << 24)
+        stage = {}
+        for L, i in enumerate(ids):
+            if i >= nwin:
+                continue
+            st, tok, out, _ = ms[L]
+            lim = min(nxt[L][2], ntok)
+            slot, o = pad + out - o_first, out
+            for p in range(max(0, i * W - mis0), min(n, i * W - mis0 + W)):
+                y = ent(st, w[p])
+                if staged:
+                    if y & COUNT:
+                        stage[slot] = (((p - P) & 0xFFFFFF) << 8) | ((y >> 24) & 0xFF)
+                        slot += 1
+                else:
+                    if (y & COUNT) and o < lim:
+                        kinds[o], lens[o], offs[o] = (y >> 24) & 0xFF, p - tok, tok
+                        o += 1
+                    if y & EMIT:
+                        tok = p
+                st = (y & ROWMASK) >> 2
+            # the input's end, or a lane starting at the next window: the token ends here
+            if (i + 1 == nwin or nxt[L][3]) and st != 0:
+                end = n if i + 1 == nwin else (i + 1) * W - mis0
+                r = st >> 8
+                if (info[r] & INFO_ACC) and (info[r] & INFO_COUNT):
+                    if staged:
+                        stage[slot] = int(kind[r]) | ((end - P) << 8)
+                    elif o < lim:
+                        kinds[o], lens[o], offs[o] = int(kind[r]), end - tok, tok
+        if not staged:
+            continue
+        o0 = o_first - pad
+        for q in range(0, pad + total, 4):
+            prev = stage[q - 1] >> 8 if q > pad else 0
+            for k in range(4):
+                g = q + k
+                endp = stage.get(g, 0) >> 8
+                pv = prev if g > pad else 0
+                if pad <= g < pad + total:
+                    kinds[o0 + g], lens[o0 + g], offs[o0 + g] = stage[g] & 0xFF, endp - pv, P + pv
+                prev = endp
+    return kinds, lens, offs

@@ -41,6 +41,11 @@ def test_host_side_argument_checks():
     bad = P.RunOpts(lane_bytes=1024, chunk_bytes=1000)  # lanes must divide chunks
     assert L.lex_workspace_size(lx._h, 1 << 20, 0, C.byref(bad)) == 0
     assert L.lex_workspace_size(lx._h, 1 << 33, 0, None) == 0  # beyond 32-bit offsets
+    bad = P.RunOpts(emit=5)  # unknown emit choice
+    assert L.lex_workspace_size(lx._h, 1 << 20, 0, C.byref(bad)) == 0
+    # the windowed emit keeps checkpoints: a larger workspace than the lane emit
+    lane = P.RunOpts(emit=P.LEX_EMIT_LANE)
+    assert lx.workspace_size(1 << 20, 0) > L.lex_workspace_size(lx._h, 1 << 20, 0, C.byref(lane)) > 0
     rc = L.lex_run(lx._h, None, 10, 0, None, None, None, 0, None, None, 0, None, None)
     assert rc == P.LEX_EINVAL
     assert lx.workspace_size(1 << 20, 0) > 0

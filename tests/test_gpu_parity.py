@@ -63,18 +63,36 @@ def check(name, buf, mode, opts=None, pad_front=0, offsets=True, label=""):
     return r
 
 
-def opts(lane, path):
-    return P.RunOpts(lane_bytes=lane, path=path)
+def opts(lane, path, emit=0):
+    return P.RunOpts(lane_bytes=lane, path=path, emit=emit)
 
 
 CL = workloads.clike(1 << 20, 1)  # the 1 MiB config, seed 1
 
 
+@pytest.mark.parametrize("emit", [P.LEX_EMIT_DEFAULT, P.LEX_EMIT_LANE])
 @pytest.mark.parametrize("path", [1, 2])
 @pytest.mark.parametrize("lane", [16, 64, 256, 1024, 4096, 0])
-def test_clike_1mib_exact(path, lane):
-    r = check("clike_l", CL, P.LEX_MODE_EXACT, opts(lane, path))
+def test_clike_1mib_exact(path, lane, emit):
+    r = check("clike_l", CL, P.LEX_MODE_EXACT, opts(lane, path, emit))
     assert r.nslices > 1
+
+
+@pytest.mark.parametrize("path", [1, 2])
+def test_windowed_dense_tokens_direct(path):
+    """One-byte tokens: every wave's output range outgrows its LDS stage, so the windowed
+    emit writes token by token."""
+    dense = np.frombuffer(b"a;b;" * 50000 + b"\n" + b"x=1;" * 30000, np.uint8)
+    for lane in (64, 1024):
+        check("clike_l", dense, P.LEX_MODE_EXACT, opts(lane, path))
+
+
+def test_windowed_long_slice_falls_back():
+    """A slice of 2^24 bytes or more (one 17 MiB comment) keeps no checkpoints: the lane
+    emit takes the scan."""
+    big = np.concatenate([CL[:5000], np.frombuffer(b"// ", np.uint8),
+                          np.full(17 << 20, ord("c"), np.uint8), np.frombuffer(b"\n", np.uint8), CL[:7000]])
+    check("clike_l", big, P.LEX_MODE_EXACT, opts(1024, 2), offsets=False)
 
 
 @pytest.mark.parametrize("path", [1, 2])

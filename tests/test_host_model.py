@@ -64,3 +64,36 @@ def test_nonmonotone_fallback_cases():
     cb = T.as_tuples(T.CLIKE_B)
     _check(cb, [b"/*a", b"/* a\nb */", b"a/*b*/c", b"/**/", b"/*/", b"x /* y", b"//a\n/*"], rng)
     assert not P.Lexer.compile(js).info()["monotone"]
+
+
+def test_windowed_emit_model():
+    """The windowed emit's bookkeeping (window checkpoints, owner lookup, tiles, staged
+    flush) restated on the host gives the oracle's tokens: monotone sets whose token ends are
+    all counted, both planners' slice conventions, several lane lengths, buffer alignments
+    and stage sizes (small stages force the direct path), and inputs with long tokens that
+    leave lanes empty."""
+    long_tok = b"x = 1;\n/* " + b"c" * 3000 + b" */\ny = 2;\n" + b"s = \"" + b"q" * 700 + b"\";\nz;\n"
+    cases = [("clike_l", bytes(workloads.clike(20000, 3)), 0),
+             ("clike_l", bytes(workloads.clike(3000, 4)) + long_tok + bytes(workloads.clike(3000, 5)), 0),
+             ("log", bytes(workloads.loglines(12000, 37)), 0),
+             ("clike_d", bytes(workloads.clike(9000, 6)), 0)]
+    for name, w, mode in cases:
+        defs = T.as_tuples(T.NAMED[name])
+        lx, oc = P.Lexer.compile(defs), oracle.OracleSet(defs)
+        m = hostmodel.Model(lx, mode)
+        k, l, offs, con = oc.lex(w, discard=bool(mode), offsets=True)
+        want = (k.tolist(), l.tolist(), offs.tolist())
+        cert = lx.cert(mode)
+        for lane in (64, 256, 1024, 1 << 20):
+            cuts = hostmodel.plan_cuts(w, cert, lane)
+            plans = [(cuts[:-1], cuts[1:]), hostmodel.plan_fused(w, cert, lane)]
+            for starts, ends in plans:
+                for base in (0, 3, 63):
+                    for stage in (1280, 150):
+                        got = hostmodel.windowed(m, w, starts, ends, lane, base, 4, stage)
+                        assert got == want, (name, lane, base, stage)
+        # a slice that halts: the windowed emit stands down
+        bad = w[:3000] + b"\x01" + w[3000:]
+        if oc.lex(bad, discard=bool(mode))[2] < len(bad):
+            cuts = hostmodel.plan_cuts(bad, cert, 256)
+            assert hostmodel.windowed(m, bad, cuts[:-1], cuts[1:], 256, 0) is None
