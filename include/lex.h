@@ -123,9 +123,9 @@ int lex_tables(const lex_dfa *dfa, int mode, uint32_t *table, size_t table_entri
 /* Tuning of one scan (NULL = defaults).  chunk_bytes: target length of the paper's
  * equal-division chunks (boundaries slide forward to the next certified byte); lane_bytes:
  * target length of the sub-slices one GPU lane walks (a multiple of 16 and a divisor of
- * chunk_bytes; 0 = chosen from n).  path: 0 = default, 1 = the five-step pipeline
- * (bitmap, plan, count walk, scan, emit walk), 2 = fused (each lane finds its own cut,
- * no bitmap).  block_threads: threads per walk workgroup, 256, 512 or 1024 (0 = the
+ * chunk_bytes; 0 = chosen from n).  path: 0 = default (fused), 1 = the five-step
+ * pipeline (bitmap, plan, count walk, scan, emit walk), 2 = fused (each lane finds its own
+ * cut, no bitmap).  block_threads: threads per walk workgroup, 256, 512 or 1024 (0 = the
  * largest whose LDS fits).  emit: 0 = default, 1 = lane emit only.  By default a scan
  * whose automaton is monotone (no live edge from an accepting to a non-accepting state),
  * counts every token end in its mode (exact mode, or no discarded kind) and has at most

@@ -192,16 +192,33 @@ __global__ void __launch_bounds__(256) k_plan(const uint64_t *__restrict__ bits,
 }
 
 // ----------------------------------------------------------- (c), (e) walk
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+typedef __attribute__((address_space(3))) uint8_t lds_u8;
+
 struct Tables {
-  const uint32_t *T;    // LDS, at LDS address 0
+  const lds_u8 *T;      // LDS table, byte-addressed (so that (e & mask) ^ (b << 2) is one
+                        // bit operation and the table's LDS offset an immediate)
   const uint8_t *info;  // LDS
   const uint8_t *kind;  // LDS
   uint32_t sink, fail;  // row byte offsets (fail == sink when monotone)
 };
 
 __device__ __forceinline__ uint32_t entry(const Tables &tb, uint32_t st, uint32_t b) {
-  return *reinterpret_cast<const uint32_t *>(reinterpret_cast<const uint8_t *>(tb.T) + (st ^ (b << 2)));
+  return *reinterpret_cast<const lds_u32 *>(tb.T + (st ^ (b << 2)));
 }
+
+// The same lookup from the previous entry itself (its row bits, masked in the same
+// instruction): (e & kRowMask) ^ (b << 2) as one v_bitop3 (truth table 0x6C over the
+// operands e, b << 2, kRowMask), used directly as the LDS address.  This relies on the
+// table sitting at LDS address 0: the walk kernels declare no static LDS, so their
+// dynamic LDS, whose first bytes carve_lds gives the table, starts there.  (Adding the
+// table's address instead costs a v_add per byte: it is only known to be 0 after
+// instruction selection.)
+__device__ __forceinline__ uint32_t entry_from(const Tables &, uint32_t e, uint32_t b) {
+  return *(const lds_u32 *)(size_t)__builtin_amdgcn_bitop3_b32(e, b << 2, kRowMask, 0x6C);
+}
+
+__device__ __forceinline__ const lds_u8 *lds_bytes_of(const void *p) { return (const lds_u8 *)p; }
 
 // Emit-side per-lane state.  The lane owns output slots [first, first + count).
 //
@@ -459,14 +476,13 @@ __device__ __forceinline__ void block16(LaneState &L, Ring &r, const Tables &tb,
   if (!EMIT && MONO) {
     // count walk of a monotone automaton: the COUNT bits of the 16 steps are shifted
     // into m (bit 0 of each entry lands in bit 31) and popcounted once.
-    uint32_t m = 0, st = L.st;
+    uint32_t m = 0, e = L.st;
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
-      const uint32_t e = entry(tb, st, byte_of(v, k));
-      st = e & kRowMask;
+      e = entry_from(tb, e, byte_of(v, k));
       m = __builtin_amdgcn_alignbit(e, m, 1);
     }
-    L.st = st;
+    L.st = e & kRowMask;
     L.cnt += __builtin_popcount(m);
     // start of the token in progress: the last step whose token ended (bit 16 + k
     // holds step k); only read by checkpoints, whose tables count every token end
@@ -609,8 +625,9 @@ struct WalkArgs {
   uint64_t cap;
 };
 
-// Dynamic LDS layout of the walk kernels (no static LDS, so the table sits at LDS
-// address 0): table | rowinfo | rowkind | lut (256) | reduction scratch | ring.
+// Dynamic LDS layout of the walk kernels: table | rowinfo | rowkind | lut (256) |
+// reduction scratch | ring or stage.  The walk kernels must declare no static LDS, so that
+// the table sits at LDS address 0 (entry_from addresses it absolutely).
 struct Lds {
   uint32_t *T;
   uint8_t *info, *kind, *lut;
@@ -733,7 +750,7 @@ template <bool MONO, bool FUSED, bool CK>
 __global__ void __launch_bounds__(1024) k_count(WalkArgs a) {
   const Lds l = carve_lds(a.nrows);
   stage_tables(a, l, FUSED);
-  const Tables tb{l.T, l.info, l.kind, a.sink, a.fail};
+  const Tables tb{lds_bytes_of(l.T), l.info, l.kind, a.sink, a.fail};
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
   uint32_t cnt = 0, fail = kNone, nonempty = 0, big = 0;
   uint32_t s = 0, e = 0;
@@ -908,7 +925,7 @@ __global__ void __launch_bounds__(1024) k_emit(WalkArgs a) {
   if (j0 > first) return;  // the whole block lies after the first halted lane
   const Lds l = carve_lds(a.nrows);
   stage_tables(a, l, FUSED);
-  const Tables tb{l.T, l.info, l.kind, a.sink, a.fail};
+  const Tables tb{lds_bytes_of(l.T), l.info, l.kind, a.sink, a.fail};
   const uint32_t j = j0 + threadIdx.x;
   if (j >= a.nlanes || j > first) return;
   const uint64_t off = a.blk_sum[blockIdx.x] + a.lane_pre[j];
@@ -967,7 +984,7 @@ __device__ __forceinline__ void wave_sync() {
 
 __device__ __forceinline__ uint32_t row_state(uint32_t row) { return (row << kRowShift) | ((row & 31u) << 2); }
 
-// First-round loads for the window starting at position ws (owner candidates, checkpoint).
+// First-round loads for window i (owner candidates).
 struct WinR1 {
   uint32_t ws, j0, s0, e0;
   int32_t lz, bz;  // last non-empty lane at or before j0 - 1: in its workgroup; before it
@@ -986,56 +1003,53 @@ __device__ __forceinline__ WinR1 win_r1(const WalkArgs &a, uint32_t i, uint32_t 
   return r;
 }
 
-// Second round: the owner's output offset.  Window nwin (past the end) gives ntok.
+// Second round: the state at the window's start and its first output slot (offsets fit
+// 32 bits: a scan has fewer than 2^32 tokens).  Window nwin (past the end) gives ntok.
 struct WinMeta {
-  uint32_t st, tok;
-  uint64_t out;
-  bool fresh;  // a lane starts at the window's first byte
+  uint32_t st, tok, out;
+  uint32_t fresh;  // a lane starts at the window's first byte
 };
 
 __device__ __forceinline__ WinMeta win_meta(const WalkArgs &a, const WinR1 &r, uint32_t i, uint32_t nwin,
-                                            uint64_t ntok) {
-  WinMeta m{0, 0, ntok, false};
+                                            uint32_t ntok) {
+  WinMeta m{0, 0, ntok, 0};
   if (i >= nwin) return m;
   const bool here = r.s0 < r.e0 && r.s0 <= r.ws;
   const uint32_t owner = here ? r.j0 : (uint32_t)(r.lz >= 0 ? r.lz : r.bz);
-  const uint64_t base = a.blk_sum[owner / a.block] + a.lane_pre[owner];
-  const bool fresh = here && r.s0 == r.ws;
-  uint2 c = make_uint2(0, 0);
-  if (!fresh) {
-    const uint32_t k = (r.ws - owner * a.lane_bytes) / kWin;
-    c = k < a.kslots ? a.ck[(size_t)k * a.nlanes + owner] : a.ck_over[i];
-  }
-  if (fresh) {  // the owner starts here: a fresh token
-    m.st = 0;
+  const uint32_t base = (uint32_t)a.blk_sum[owner / a.block] + a.lane_pre[owner];
+  if (here && r.s0 == r.ws) {  // the owner starts here: a fresh token
     m.tok = r.ws;
     m.out = base;
-    m.fresh = true;
-  } else {
-    m.st = row_state(c.x >> 24);
-    m.tok = c.y;
-    m.out = base + (c.x & 0xFFFFFFu);
+    m.fresh = 1;
+    return m;
   }
+  const uint32_t k = (r.ws - owner * a.lane_bytes) / kWin;
+  const uint2 c = k < a.kslots ? a.ck[(size_t)k * a.nlanes + owner] : a.ck_over[i];
+  m.st = row_state(c.x >> 24);
+  m.tok = c.y;
+  m.out = base + (c.x & 0xFFFFFFu);
   return m;
 }
 
 // Output of the staged and the direct walk.
 struct WinOut {
-  uint32_t g, d;       // staged: spill slot address, distance to the next slot
+  uint32_t A, G;       // staged: LDS address of the next slot, of the lane's spill word
   uint32_t base;       // staged: P
   uint32_t tok;        // direct: start of the token in progress
-  uint64_t o, lim;     // direct: next output slot, end of the thread's range
+  uint32_t o, lim;     // direct: next output slot, end of the thread's range
 };
 
+// st carries the previous entry unmasked (or a row state); mask it before reading a row.
 template <bool STAGED>
 __device__ __forceinline__ void win_step(const Tables &tb, const WalkArgs &a, uint32_t &st, WinOut &w, uint32_t b,
                                          uint32_t p) {
-  const uint32_t e = entry(tb, st, b);
+  const uint32_t e = entry_from(tb, st, b);
   if (STAGED) {
-    const uint32_t c = e & kCountBit;
-    *(__attribute__((address_space(3))) uint32_t *)(size_t)(w.g + c * w.d) =
-        __builtin_amdgcn_perm(e, p - w.base, 0x02010007u);
-    w.d += c << 2;
+    // every step writes its word: to the next slot when a counted token ends here (the
+    // slot then advances), else to the lane's spill word
+    const bool c = (e & kCountBit) != 0;
+    *(lds_u32 *)(size_t)(c ? w.A : w.G) = __builtin_amdgcn_perm(e, p - w.base, 0x02010007u);
+    w.A += c ? 4u : 0u;
   } else {
     if ((e & kCountBit) && w.o < w.lim) {
       a.kinds[w.o] = (uint8_t)(e >> 24);
@@ -1045,7 +1059,7 @@ __device__ __forceinline__ void win_step(const Tables &tb, const WalkArgs &a, ui
     }
     w.tok = (e & kEmitBit) ? p : w.tok;
   }
-  st = e & kRowMask;
+  st = e;
 }
 
 // The window's 64 bytes at position wp (its kWin-aligned start, possibly before 0).
@@ -1053,12 +1067,14 @@ struct Win64 {
   uint4 v[4];
 };
 
+template <bool EDGE>
 __device__ __forceinline__ Win64 win_load(const uint8_t *in, int64_t wp, uint32_t n) {
   Win64 d;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int64_t p = wp + 16 * q;
-    d.v[q] = (p >= 0 && p + 16 <= (int64_t)n) ? *reinterpret_cast<const uint4 *>(in + p) : load_block(in, p, n);
+    if (EDGE) d.v[q] = (p >= 0 && p + 16 <= (int64_t)n) ? *reinterpret_cast<const uint4 *>(in + p) : load_block(in, p, n);
+    else d.v[q] = *reinterpret_cast<const uint4 *>(in + p);
   }
   return d;
 }
@@ -1078,71 +1094,68 @@ __device__ __forceinline__ void win_walk(const Tables &tb, const WalkArgs &a, co
   }
 }
 
+// A tile is 64 windows; each wave walks a contiguous run of tiles.  Software pipeline:
+// the next tile's bytes and the state of the tile after it load while a tile walks.
 template <bool FUSED>
 __global__ void __launch_bounds__(256) k_emit_win(WalkArgs a) {
   if (a.meta[0] != kNone || a.meta[1] != 0 || a.res->status != 0 || a.n == 0) return;
   const Lds l = carve_lds(a.nrows);
   stage_tables(a, l, false);
-  const Tables tb{l.T, l.info, l.kind, a.sink, a.fail};
+  const Tables tb{lds_bytes_of(l.T), l.info, l.kind, a.sink, a.fail};
   const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   uint32_t *stage = reinterpret_cast<uint32_t *>(l.ring) + wid * kStageWords;
-  const uint32_t stage_addr = (uint32_t)(size_t)(__attribute__((address_space(3))) uint32_t *)stage;
+  const uint32_t stage_addr = (uint32_t)(size_t)(lds_u32 *)stage;
   const uintptr_t base = reinterpret_cast<uintptr_t>(a.in);
   const uint32_t mis0 = (uint32_t)(base & (kWin - 1));
   const uint32_t nwin = (uint32_t)(((uint64_t)a.n + mis0 + kWin - 1) / kWin);
   const uint32_t ntiles = (nwin + 63) / 64;
-  const uint64_t ntok = a.res->ntokens;  // every store below stays under it
-  // Each XCD (workgroups are dealt to the 8 XCDs in turn) takes a contiguous run of
-  // tiles, so neighbouring windows share its L2.
-  const uint32_t nxcd = gridDim.x >= 8 ? 8 : 1;
-  const uint32_t xcd = blockIdx.x % nxcd, per_xcd_wg = gridDim.x / nxcd;
-  const uint32_t xcd_tiles = (ntiles + nxcd - 1) / nxcd;
-  const uint32_t t_lo = xcd * xcd_tiles, t_hi = min(ntiles, t_lo + xcd_tiles);
-  const uint32_t tstep = per_xcd_wg * kWinWaves;
-  uint32_t tile = t_lo + (blockIdx.x / nxcd) * kWinWaves + wid;
-  if (blockIdx.x / nxcd >= per_xcd_wg) tile = t_hi;  // workgroups beyond a multiple of 8
-  // software pipeline: metadata and bytes of the next tile load while this one walks
-  WinR1 r1a = win_r1<FUSED>(a, tile * 64 + lane, mis0, nwin), r1b = win_r1<FUSED>(a, tile * 64 + lane + 1, mis0, nwin);
-  Win64 dat = win_load(a.in, (int64_t)tile * 64 * kWin + (int64_t)lane * kWin - mis0, a.n);
-  WinMeta ma = win_meta(a, r1a, tile * 64 + lane, nwin, ntok), mb = win_meta(a, r1b, tile * 64 + lane + 1, nwin, ntok);
-  for (; tile < t_hi; tile += tstep) {
+  const uint32_t ntok = (uint32_t)a.res->ntokens;  // every store below stays under it
+  const uint32_t nwaves = gridDim.x * kWinWaves, gw = blockIdx.x * kWinWaves + wid;
+  const uint32_t per = (ntiles + nwaves - 1) / nwaves;
+  const uint32_t t_lo = min(ntiles, gw * per), t_hi = min(ntiles, t_lo + per);
+  if (t_lo >= t_hi) return;  // wave-uniform, and no workgroup barrier follows
+  WinMeta cur = win_meta(a, win_r1<FUSED>(a, t_lo * 64 + lane, mis0, nwin), t_lo * 64 + lane, nwin, ntok);
+  WinMeta nxt = win_meta(a, win_r1<FUSED>(a, (t_lo + 1) * 64 + lane, mis0, nwin), (t_lo + 1) * 64 + lane, nwin, ntok);
+  WinR1 r1 = win_r1<FUSED>(a, (t_lo + 2) * 64 + lane, mis0, nwin);
+  auto wpos = [&](uint32_t t) { return (int64_t)t * 64 * kWin + (int64_t)lane * kWin - mis0; };
+  auto is_edge = [&](uint32_t t) { return t == 0 || t + 1 == ntiles; };
+  Win64 dat = is_edge(t_lo) ? win_load<true>(a.in, wpos(t_lo), a.n) : win_load<false>(a.in, wpos(t_lo), a.n);
+  for (uint32_t tile = t_lo; tile < t_hi; ++tile) {
     const uint32_t i = tile * 64 + lane;
-    const uint32_t next = tile + tstep;
-    const bool has_next = next < t_hi;
-    WinR1 n1a{}, n1b{};
-    Win64 ndat{};
-    if (has_next) {
-      n1a = win_r1<FUSED>(a, next * 64 + lane, mis0, nwin);
-      n1b = win_r1<FUSED>(a, next * 64 + lane + 1, mis0, nwin);
-      ndat = win_load(a.in, (int64_t)next * 64 * kWin + (int64_t)lane * kWin - mis0, a.n);
-    }
     const bool valid = i < nwin;
-    const uint64_t out = ma.out;
-    const uint64_t cnt = valid ? mb.out - ma.out : 0;
-    const uint64_t o_first = __shfl(out, 0);
-    const uint64_t o_end = __shfl(valid ? mb.out : 0, (int)min<uint32_t>(63, nwin - 1 - tile * 64));
-    const uint32_t P = __shfl(ma.tok, 0);  // start of the token in progress at the tile's start
-    const uint64_t total = o_end - o_first;
-    const uint32_t pad = (uint32_t)(o_first & 3);
-    const int64_t wp = (int64_t)i * kWin - mis0;
+    const bool edge = is_edge(tile);
+    Win64 ndat = dat;
+    if (tile + 1 < t_hi)
+      ndat = is_edge(tile + 1) ? win_load<true>(a.in, wpos(tile + 1), a.n) : win_load<false>(a.in, wpos(tile + 1), a.n);
+    // this window's range of output slots ends where the next window's begins
+    // (every shuffle runs with the whole wave active: a lane reading from an inactive
+    // lane gets no defined value)
+    const uint32_t o_first = __shfl(cur.out, 0), o_next = __shfl(nxt.out, 0);
+    const uint32_t down = __shfl_down(cur.out, 1), fdown = __shfl_down(cur.fresh, 1);
+    const uint32_t f_next = __shfl(nxt.fresh, 0);
+    const uint32_t out_end = lane < 63 ? down : o_next;
+    const uint32_t next_fresh = lane < 63 ? fdown : f_next;
+    const uint32_t P = __shfl(cur.tok, 0);  // start of the token in progress at the tile's start
+    const uint32_t total = o_next - o_first;
+    const uint32_t pad = o_first & 3;
+    const int64_t wp = wpos(tile);
     const uint32_t span_end = (uint32_t)min<int64_t>((int64_t)(tile + 1) * 64 * kWin - mis0, a.n);
-    const bool staged = o_first <= o_end && o_end <= ntok && total + pad + 3 <= kStageWords - 64 &&
+    const bool staged = o_first <= o_next && o_next <= ntok && total + pad + 3 <= kStageWords - 64 &&
                         span_end - P < (1u << 24);
-    const bool edge = tile == 0 || tile + 1 == ntiles;  // a window reaching outside [0, n)
-    uint32_t st = ma.st;
+    uint32_t st = cur.st;
     WinOut w;
     if (staged) {
-      w.g = stage_addr + 4 * (kStageWords - 64 + lane);  // spill slots: the stage's last 64 words
-      w.d = stage_addr + 4 * (pad + (uint32_t)(out - o_first)) - w.g;
+      w.G = stage_addr + 4 * (kStageWords - 64 + lane);  // spill words: the stage's last 64
+      w.A = stage_addr + 4 * (pad + (cur.out - o_first));
       w.base = P;
       if (valid) {
         if (edge) win_walk<true, true>(tb, a, dat, wp, a.n, st, w);
         else win_walk<true, false>(tb, a, dat, wp, a.n, st, w);
       }
     } else {
-      w.tok = ma.tok;
-      w.o = out;
-      w.lim = min(out + cnt, ntok);
+      w.tok = cur.tok;
+      w.o = cur.out;
+      w.lim = valid ? min(out_end, ntok) : cur.out;
       if (valid) {
         if (edge) win_walk<false, true>(tb, a, dat, wp, a.n, st, w);
         else win_walk<false, false>(tb, a, dat, wp, a.n, st, w);
@@ -1151,13 +1164,13 @@ __global__ void __launch_bounds__(256) k_emit_win(WalkArgs a) {
     // The input's end, or a lane starting at the next window's first byte: the token in
     // progress ends here, as the lane walk's slice end made it (the next window starts
     // afresh and does not see it).
-    if (valid && (i + 1 == nwin || mb.fresh) && st != 0) {
+    st &= kRowMask;
+    if (valid && (i + 1 == nwin || next_fresh) && st != 0) {
       const uint32_t end = i + 1 == nwin ? a.n : (i + 1) * kWin - mis0;
       const uint32_t row = st >> kRowShift;
       if ((tb.info[row] & kInfoAcc) && (tb.info[row] & kInfoCount)) {
         if (staged) {
-          *(__attribute__((address_space(3))) uint32_t *)(size_t)(w.g + w.d) =
-              (uint32_t)tb.kind[row] | ((end - P) << 8);
+          *(lds_u32 *)(size_t)w.A = (uint32_t)tb.kind[row] | ((end - P) << 8);
         } else if (w.o < w.lim) {
           a.kinds[w.o] = tb.kind[row];
           a.lens[w.o] = end - w.tok;
@@ -1165,28 +1178,24 @@ __global__ void __launch_bounds__(256) k_emit_win(WalkArgs a) {
         }
       }
     }
-    // the next tile's owner offsets, before this tile's stores
-    WinMeta nma{}, nmb{};
-    if (has_next) {
-      nma = win_meta(a, n1a, next * 64 + lane, nwin, ntok);
-      nmb = win_meta(a, n1b, next * 64 + lane + 1, nwin, ntok);
-    }
+    // the state of the tile after next, before this tile's stores
+    const WinMeta n2 = win_meta(a, r1, (tile + 2) * 64 + lane, nwin, ntok);
+    r1 = win_r1<FUSED>(a, (tile + 3) * 64 + lane, mis0, nwin);
     if (staged) {
       wave_sync();
       // write the range out: slot q holds output o_first - pad + q
-      const uint64_t o0 = o_first - pad;
+      const uint32_t o0 = o_first - pad;
       for (uint32_t q = lane * 4; q < pad + total; q += 256) {
         const uint4 v = *reinterpret_cast<const uint4 *>(stage + q);
         const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
         uint32_t prev = q > pad ? stage[q - 1] >> 8 : 0;
-        uint32_t len[4], kd = 0;
-        uint64_t st4[4];
+        uint32_t len[4], kd = 0, sp[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
           const uint32_t endp = wv[k] >> 8;
           const uint32_t pv = q + k > pad ? prev : 0;
           len[k] = endp - pv;
-          st4[k] = (uint64_t)P + pv;
+          sp[k] = P + pv;
           kd |= (wv[k] & 0xFFu) << (8 * k);
           prev = endp;
         }
@@ -1195,7 +1204,7 @@ __global__ void __launch_bounds__(256) k_emit_win(WalkArgs a) {
           *reinterpret_cast<uint32_t *>(a.kinds + o0 + q) = kd;
           if (a.offs) {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) a.offs[o0 + q + k] = st4[k];
+            for (int k = 0; k < 4; ++k) a.offs[o0 + q + k] = sp[k];
           }
         } else {
 #pragma unroll
@@ -1203,15 +1212,15 @@ __global__ void __launch_bounds__(256) k_emit_win(WalkArgs a) {
             if (q + k >= pad && q + k < pad + total) {
               a.lens[o0 + q + k] = len[k];
               a.kinds[o0 + q + k] = (uint8_t)(kd >> (8 * k));
-              if (a.offs) a.offs[o0 + q + k] = st4[k];
+              if (a.offs) a.offs[o0 + q + k] = sp[k];
             }
           }
         }
       }
       wave_sync();
     }
-    ma = nma;
-    mb = nmb;
+    cur = nxt;
+    nxt = n2;
     dat = ndat;
   }
 }

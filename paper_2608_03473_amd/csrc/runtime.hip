@@ -164,7 +164,7 @@ int resolve(const lex_dfa *d, uint64_t n, int mode, const lex_run_opts *o, Resol
   if (mode < 0 || mode > 3) return LEX_EINVAL;
   r.table = mode & 1;
   r.serial = (mode & 2) != 0 || d->cm[r.table].nbytes == 0;
-  r.path = o && o->path ? o->path : 1;
+  r.path = o && o->path ? o->path : 2;  // fused planning by default
   if (r.path != 1 && r.path != 2) return LEX_EINVAL;
   r.block = o && o->block_threads ? (uint32_t)o->block_threads : default_block(d->c.nrows);
   const int emit = o ? o->emit : LEX_EMIT_DEFAULT;

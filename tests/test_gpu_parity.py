@@ -87,6 +87,19 @@ def test_windowed_dense_tokens_direct(path):
         check("clike_l", dense, P.LEX_MODE_EXACT, opts(lane, path))
 
 
+@pytest.mark.parametrize("pad", [0, 1, 63])
+def test_windowed_lane_starts_on_tile_boundaries(pad):
+    """A certified byte (LF) at every multiple of 4096 bytes: lanes start exactly where a
+    64-window tile of the windowed emit begins, so the token ending there is closed by the
+    previous tile's last window; with the buffer offset the boundaries shift."""
+    b = np.array(CL[: 1 << 19], copy=True)
+    b[4096::4096] = ord("\n")
+    b[4096 * 3 - 1] = ord("\n")  # and one just before a boundary
+    for lane in (64, 1024, 4096):
+        for path in (1, 2):
+            check("clike_l", b, P.LEX_MODE_EXACT, opts(lane, path), pad_front=pad)
+
+
 def test_windowed_long_slice_falls_back():
     """A slice of 2^24 bytes or more (one 17 MiB comment) keeps no checkpoints: the lane
     emit takes the scan."""
