@@ -45,6 +45,18 @@ constexpr uint8_t kInfoAcc = 0x80;
 constexpr uint8_t kInfoCount = 0x40;
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr uint32_t kTile = 4096;        // bytes per bitmap tile (64 words)
+
+// Unsigned division by a divisor d >= 2 fixed for a launch, by multiplication
+// (Granlund and Montgomery, "Division by invariant integers using multiplication", 1994):
+// with l = ceil(log2 d) and m = floor(2^32 (2^l - d) / d) + 1, n / d = (t + ((n - t) >> 1))
+// >> (l - 1) where t = mulhi(n, m), for every 32-bit n.
+struct FastDiv {
+  uint32_t m, l;
+};
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, FastDiv f) {
+  const uint32_t t = __umulhi(n, f.m);
+  return (t + ((n - t) >> 1)) >> (f.l - 1);
+}
 constexpr uint32_t kTilesPerBlock = 1024;
 
 __host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -615,6 +627,8 @@ struct WalkArgs {
   int32_t *lnz;           // per lane: last non-empty lane at or before it in its workgroup, or -1
   int32_t *blk_lnz;       // per workgroup: last non-empty lane (count); before it (after the scan)
   uint32_t block;         // lanes per count workgroup (lane_pre's groups)
+  uint32_t block_shift;   // log2(block)
+  FastDiv lane_div;       // division by lane_bytes
   int fallback_only;      // lane emit: run only when the windowed emit cannot
   // emit
   const uint32_t *meta;
@@ -963,8 +977,8 @@ __global__ void __launch_bounds__(1024) k_emit(WalkArgs a) {
 // a contiguous range of output slots.  The wave stages that range in LDS as words
 // (end - P) << 8 | kind, P being the start of the range's first token, and writes it out
 // with 16-byte stores; lengths are the differences of consecutive ends.  A range longer
-// than the stage (less its 64 spill words), or spanning 2^24 bytes or more, is written
-// token by token instead.
+// than the stage (less its 64 spill words, which come first), or spanning 2^24 bytes or
+// more, is written token by token instead.
 //
 // A window's output offset comes from the lane that owns its first byte: lane j0 =
 // start / lane_bytes when that lane is not empty and starts at or before it, otherwise
@@ -995,11 +1009,11 @@ __device__ __forceinline__ WinR1 win_r1(const WalkArgs &a, uint32_t i, uint32_t 
   WinR1 r{};
   if (i >= nwin) return r;
   r.ws = i ? i * kWin - mis0 : 0;
-  r.j0 = min(r.ws / a.lane_bytes, a.nlanes - 1);
+  r.j0 = min(fdiv(r.ws, a.lane_div), a.nlanes - 1);
   r.s0 = a.cuts[r.j0];
   r.e0 = FUSED ? a.ends[r.j0] : a.cuts[r.j0 + 1];
   r.lz = r.j0 ? a.lnz[r.j0 - 1] : -1;
-  r.bz = r.j0 ? a.blk_lnz[(r.j0 - 1) / a.block] : -1;
+  r.bz = r.j0 ? a.blk_lnz[(r.j0 - 1) >> a.block_shift] : -1;
   return r;
 }
 
@@ -1016,7 +1030,7 @@ __device__ __forceinline__ WinMeta win_meta(const WalkArgs &a, const WinR1 &r, u
   if (i >= nwin) return m;
   const bool here = r.s0 < r.e0 && r.s0 <= r.ws;
   const uint32_t owner = here ? r.j0 : (uint32_t)(r.lz >= 0 ? r.lz : r.bz);
-  const uint32_t base = (uint32_t)a.blk_sum[owner / a.block] + a.lane_pre[owner];
+  const uint32_t base = (uint32_t)a.blk_sum[owner >> a.block_shift] + a.lane_pre[owner];
   if (here && r.s0 == r.ws) {  // the owner starts here: a fresh token
     m.tok = r.ws;
     m.out = base;
@@ -1033,7 +1047,8 @@ __device__ __forceinline__ WinMeta win_meta(const WalkArgs &a, const WinR1 &r, u
 
 // Output of the staged and the direct walk.
 struct WinOut {
-  uint32_t A, G;       // staged: LDS address of the next slot, of the lane's spill word
+  uint32_t D, G;       // staged: LDS address of the lane's spill word G, and D such that
+                       // G + D is the address of the next slot
   uint32_t base;       // staged: P
   uint32_t tok;        // direct: start of the token in progress
   uint32_t o, lim;     // direct: next output slot, end of the thread's range
@@ -1046,10 +1061,13 @@ __device__ __forceinline__ void win_step(const Tables &tb, const WalkArgs &a, ui
   const uint32_t e = entry_from(tb, st, b);
   if (STAGED) {
     // every step writes its word: to the next slot when a counted token ends here (the
-    // slot then advances), else to the lane's spill word
-    const bool c = (e & kCountBit) != 0;
-    *(lds_u32 *)(size_t)(c ? w.A : w.G) = __builtin_amdgcn_perm(e, p - w.base, 0x02010007u);
-    w.A += c ? 4u : 0u;
+    // slot then advances), else to the lane's spill word.  G + c * D with c in {0, 1} is
+    // one 24-bit multiply-add, and the write needs no branch.  (Writing only on token
+    // ends saves LDS traffic but costs more in exec-mask handling than it saves.)
+    const uint32_t c = e & kCountBit;
+    __builtin_assume(w.D < 4 * kStageWords);  // the slots lie above the spill words
+    *(lds_u32 *)(size_t)(__umul24(c, w.D) + w.G) = __builtin_amdgcn_perm(e, p - w.base, 0x02010007u);
+    w.D += c << 2;
   } else {
     if ((e & kCountBit) && w.o < w.lim) {
       a.kinds[w.o] = (uint8_t)(e >> 24);
@@ -1145,8 +1163,9 @@ __global__ void __launch_bounds__(256) k_emit_win(WalkArgs a) {
     uint32_t st = cur.st;
     WinOut w;
     if (staged) {
-      w.G = stage_addr + 4 * (kStageWords - 64 + lane);  // spill words: the stage's last 64
-      w.A = stage_addr + 4 * (pad + (cur.out - o_first));
+      // spill words: the stage's first 64; slots follow, so 0 < D < 4 * kStageWords
+      w.G = stage_addr + 4 * lane;
+      w.D = 4 * (64 - lane + pad + (cur.out - o_first));
       w.base = P;
       if (valid) {
         if (edge) win_walk<true, true>(tb, a, dat, wp, a.n, st, w);
@@ -1170,7 +1189,7 @@ __global__ void __launch_bounds__(256) k_emit_win(WalkArgs a) {
       const uint32_t row = st >> kRowShift;
       if ((tb.info[row] & kInfoAcc) && (tb.info[row] & kInfoCount)) {
         if (staged) {
-          *(lds_u32 *)(size_t)w.A = (uint32_t)tb.kind[row] | ((end - P) << 8);
+          *(lds_u32 *)(size_t)(w.G + w.D) = (uint32_t)tb.kind[row] | ((end - P) << 8);
         } else if (w.o < w.lim) {
           a.kinds[w.o] = tb.kind[row];
           a.lens[w.o] = end - w.tok;
@@ -1185,10 +1204,11 @@ __global__ void __launch_bounds__(256) k_emit_win(WalkArgs a) {
       wave_sync();
       // write the range out: slot q holds output o_first - pad + q
       const uint32_t o0 = o_first - pad;
+      const uint32_t *slots = stage + 64;
       for (uint32_t q = lane * 4; q < pad + total; q += 256) {
-        const uint4 v = *reinterpret_cast<const uint4 *>(stage + q);
+        const uint4 v = *reinterpret_cast<const uint4 *>(slots + q);
         const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
-        uint32_t prev = q > pad ? stage[q - 1] >> 8 : 0;
+        uint32_t prev = q > pad ? slots[q - 1] >> 8 : 0;
         uint32_t len[4], kd = 0, sp[4];
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
@@ -1363,6 +1383,14 @@ static WalkArgs walk_args(const DevTable &t, const CertMap &cm, const uint8_t *i
   a.lnz = p.lnz;
   a.blk_lnz = p.blk_lnz;
   a.block = p.block;
+  a.block_shift = (uint32_t)__builtin_ctz(p.block);
+  {
+    const uint32_t d = p.lane_bytes;  // >= 16
+    uint32_t l = 0;
+    while ((1ull << l) < d) ++l;
+    a.lane_div.l = l;
+    a.lane_div.m = (uint32_t)(((1ull << 32) * ((1ull << l) - d)) / d + 1);
+  }
   a.meta = p.meta;
   a.res = res;
   a.kinds = kinds;

@@ -72,7 +72,7 @@ CL = workloads.clike(1 << 20, 1)  # the 1 MiB config, seed 1
 
 @pytest.mark.parametrize("emit", [P.LEX_EMIT_DEFAULT, P.LEX_EMIT_LANE])
 @pytest.mark.parametrize("path", [1, 2])
-@pytest.mark.parametrize("lane", [16, 64, 256, 1024, 4096, 0])
+@pytest.mark.parametrize("lane", [16, 48, 64, 256, 1024, 4096, 0])
 def test_clike_1mib_exact(path, lane, emit):
     r = check("clike_l", CL, P.LEX_MODE_EXACT, opts(lane, path, emit))
     assert r.nslices > 1
