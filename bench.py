@@ -19,6 +19,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2608_03473_amd", "csrc", "kernels.hip")
+HBM_SUMMARY = os.path.join(ROOT, "profiles", "walk_kernels_clike512_hbm.md")
 
 
 def parse():
@@ -136,7 +138,8 @@ def main():
         "phase_ms": {k: round(float(v), 4) for k, v in zip(names, ph_mean)},
         "roofline": {
             "bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(dom, n, args.lane_bytes, args.path),
             "algorithmic_bytes_per_launch": int(algo[dom]),
         },
         "cpu_baseline": None,
@@ -144,6 +147,32 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(host, args)
     print(json.dumps(out), flush=True)
+
+
+def measured_traffic(kernel, n, lane_bytes, path):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE, scaled against a plain copy), or None when the summary was
+    taken on another kernel source or another workload."""
+    import hashlib
+
+    try:
+        with open(KERNEL_SOURCE, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+        fields = {}
+        with open(HBM_SUMMARY) as f:
+            for line in f:
+                if ":" in line and not line.startswith(("|", "#", " ")):
+                    k, v = line.split(":", 1)
+                    fields[k.strip()] = v.strip()
+    except OSError:
+        return None
+    if fields.get("kernels_hip_sha256") != sha:
+        return None
+    if fields.get("workload_n") != str(n) or fields.get("lane_bytes") != str(lane_bytes or "auto") \
+            or fields.get("path") != str(path or "default"):
+        return None
+    v = fields.get(f"traffic_bytes_{kernel}")
+    return int(v) if v else None
 
 
 def cpu_baseline(host, args):
