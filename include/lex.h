@@ -164,6 +164,56 @@ int lex_run(const lex_dfa *dfa, const uint8_t *d_bytes, uint64_t n, int mode, ui
             uint32_t *d_lens, uint64_t *d_offsets, uint64_t cap, lex_result *d_result, void *d_ws,
             size_t ws_bytes, const lex_run_opts *opts, void *stream);
 
+/* ---- Batched documents (many independent scans in one launch sequence).
+ *
+ * A lex_batch holds up to 8 (lexer, mode) instances resident together on the current
+ * device: their packed tables are combined into one LDS-resident table.  Each document of
+ * a batch names its instance; it is scanned exactly as lex_run would scan it alone with
+ * that lexer and mode (cut at its own useful certified bytes: Theorem 1, Theorem 3; a
+ * document whose useful map is empty, or flagged serial, is one slice), and its result is
+ * that scan's (Corollary 1 truncation, error offset relative to the document).  Documents
+ * are independent: one's error does not affect another.  The launches use fixed grids,
+ * reset their own work queues and never synchronise with the host, so a caller may
+ * capture lex_run_batch in a hipGraph and replay it. */
+typedef struct lex_batch lex_batch;
+
+typedef struct {
+  uint64_t offset;  /* first byte of the document in d_bytes */
+  uint32_t length;  /* bytes */
+  uint16_t inst;    /* instance index given to lex_batch_create */
+  uint16_t flags;   /* bit 0: serial (one slice); other bits must be 0 */
+} lex_doc;          /* 16 bytes */
+
+typedef struct {
+  uint64_t tok_offset;   /* the document's tokens are outputs [tok_offset, tok_offset + ntokens) */
+  uint64_t ntokens;
+  uint64_t error_offset; /* con of the document, relative to its first byte; == length if complete */
+  int32_t status;        /* LEX_OK, or LEX_EOVERFLOW for every document when the batch overflows cap */
+  uint32_t nslices;      /* non-empty slices the document was cut into */
+} lex_doc_result;        /* 32 bytes */
+
+/* Builds a batch from ninst lexers and modes (LEX_MODE_EXACT or LEX_MODE_DISCARD) on the
+ * current device.  LEX_ELIMIT if more than 8 instances or the combined table does not fit
+ * in LDS beside the emit stage. */
+int lex_batch_create(const lex_dfa *const *dfas, const int32_t *modes, uint32_t ninst, lex_batch **out,
+                     char *err, size_t errlen);
+void lex_batch_free(lex_batch *batch);
+
+/* Workspace for ndocs documents over nbytes bytes (opts: lane_bytes; NULL = defaults). */
+size_t lex_batch_workspace_size(const lex_batch *batch, uint32_t ndocs, uint64_t nbytes, const lex_run_opts *opts);
+
+/* Scans the ndocs documents of d_docs (device array) over d_bytes[0, nbytes) (device).
+ * Tokens go to d_kinds / d_lens (and d_offsets, relative to each document, if non-NULL),
+ * document by document in d_docs order; d_res (device, ndocs entries) receives each
+ * document's result and *d_total (device) the batch's: ntokens = total tokens,
+ * error_offset = the number of documents that did not tokenize completely, status,
+ * nslices.  nbytes must be below 2^32 (output offsets are 32-bit on the device); every
+ * document must lie inside [0, nbytes).  Only enqueues work, on `stream`. */
+int lex_run_batch(const lex_batch *batch, const uint8_t *d_bytes, uint64_t nbytes, const lex_doc *d_docs,
+                  uint32_t ndocs, uint8_t *d_kinds, uint32_t *d_lens, uint64_t *d_offsets, uint64_t cap,
+                  lex_doc_result *d_res, lex_result *d_total, void *d_ws, size_t ws_bytes,
+                  const lex_run_opts *opts, void *stream);
+
 /* Certificate bitmap of step (a) on its own (device pointers): d_bits[i >> 6] bit (i & 63)
  * is set iff byte d_bytes[i] is in the useful map of `mode`; ceil(n / 64) u64 words. */
 int lex_cert_bitmap(const lex_dfa *dfa, const uint8_t *d_bytes, uint64_t n, int mode, uint64_t *d_bits,

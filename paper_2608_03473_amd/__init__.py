@@ -11,7 +11,8 @@ on first use and its absence is an error (there is no CPU fallback).
 from .abi import (LEX_EDEVICE, LEX_EINVAL, LEX_ELIMIT, LEX_EMIT_DEFAULT, LEX_EMIT_LANE,  # noqa: F401
                   LEX_ENOMEM, LEX_EOVERFLOW, LEX_ESYNTAX, LEX_MODE_DISCARD, LEX_MODE_EXACT,
                   LEX_MODE_SERIAL, LEX_OK, LexError, RunOpts, lib, lib_path)
-from .lexer import Lexer, RunResult  # noqa: F401
+from .lexer import DOC_DTYPE, DOC_RESULT_DTYPE, Batch, BatchResult, Lexer, RunResult  # noqa: F401
 
-__all__ = ["Lexer", "RunResult", "RunOpts", "LexError", "lib", "lib_path",
+__all__ = ["Lexer", "RunResult", "Batch", "BatchResult", "DOC_DTYPE", "DOC_RESULT_DTYPE", "RunOpts",
+           "LexError", "lib", "lib_path",
            "LEX_MODE_EXACT", "LEX_MODE_DISCARD", "LEX_MODE_SERIAL"]

@@ -95,4 +95,30 @@ hipError_t run_fused(const DevTable &t, const CertMap &cm, const uint8_t *cert_l
                      const Plan &p, bool serial, uint8_t *kinds, uint32_t *lens, uint64_t *offs, uint64_t cap,
                      ResultDev *res, hipStream_t s, hipEvent_t const *ev);
 
+// Batched documents.  The instances' tables are rebased into one combined table (rows of
+// instance k follow those of instances 0..k-1); start/sink/fail are row byte offsets in it.
+constexpr int kBatchMaxInst = 8;
+struct BatchInstHost {
+  uint32_t start, sink, fail;
+  uint32_t mono, refused;
+  CertMap cm;
+};
+struct BatchTables {
+  const uint32_t *table;   // device, nrows * 256
+  const uint8_t *rowinfo;  // device, nrows
+  const uint8_t *rowkind;  // device, nrows
+  const uint8_t *luts;     // device, ninst * 256
+  int nrows;
+  uint32_t ninst;
+  BatchInstHost inst[kBatchMaxInst];
+};
+// Workspace of a batch of ndocs documents over nbytes bytes with lane target lane_bytes.
+size_t batch_workspace_bytes(uint32_t ndocs, uint64_t nbytes, uint32_t lane_bytes);
+// LDS of the batched emit workgroup (the count walk needs less): 0 if it does not fit.
+size_t batch_emit_lds_bytes(int nrows, uint32_t ninst);
+// docs: device array of 16-byte lex_doc; res: device array of 32-byte lex_doc_result.
+hipError_t run_batch(const BatchTables &bt, const uint8_t *bytes, uint64_t nbytes, const void *docs, uint32_t ndocs,
+                     uint32_t lane_bytes, uint8_t *kinds, uint32_t *lens, uint64_t *offs, uint64_t cap, void *res,
+                     ResultDev *total, void *ws, size_t ws_bytes, hipStream_t s, hipEvent_t const *ev);
+
 }  // namespace lexk

@@ -213,6 +213,7 @@ struct Tables {
   const uint8_t *info;  // LDS
   const uint8_t *kind;  // LDS
   uint32_t sink, fail;  // row byte offsets (fail == sink when monotone)
+  uint32_t start;       // row offset of the token-start row (0 unless several tables share LDS)
 };
 
 __device__ __forceinline__ uint32_t entry(const Tables &tb, uint32_t st, uint32_t b) {
@@ -397,7 +398,7 @@ __device__ __forceinline__ void recover(LaneState &L, Ring &r, const Tables &tb,
       const uint32_t row = L.lrow >> kRowShift;
       if (tb.info[row] & kInfoCount) put<EMIT>(L, r, tb.kind[row], L.lacc);
       L.tok = L.lacc;
-      L.st = 0;
+      L.st = tb.start;
       for (uint32_t p = L.tok; p < upto; ++p) {
         step<EMIT, false>(L, r, tb, in[p], p);
         if (L.st == tb.fail) break;
@@ -417,13 +418,13 @@ __device__ __forceinline__ bool finish(LaneState &L, Ring &r, const Tables &tb, 
       recover<EMIT>(L, r, tb, in, end);
       continue;
     }
-    if (L.st == 0) return false;
+    if (L.st == tb.start) return false;
     if (L.st == tb.sink) return true;
     const uint32_t row = L.st >> kRowShift;
     if (tb.info[row] & kInfoAcc) {
       if (tb.info[row] & kInfoCount) put<EMIT>(L, r, tb.kind[row], end);
       L.tok = end;
-      L.st = 0;
+      L.st = tb.start;
       return false;
     }
     if (MONO) {
@@ -536,10 +537,10 @@ __device__ __forceinline__ void block16(LaneState &L, Ring &r, const Tables &tb,
 template <bool EMIT, bool MONO, bool FAST, bool CK = false>
 __device__ __forceinline__ bool walk(LaneState &L, Ring &r, const Tables &tb, const uint8_t *in, uint32_t n, uint32_t s,
                      uint32_t e, const CkSink &ck = CkSink{}) {
-  L.st = 0;
+  L.st = tb.start;
   L.tok = s;
   L.lacc = s;
-  L.lrow = 0;
+  L.lrow = tb.start;
   if (s >= e) return false;
   const int64_t mis = (int64_t)(reinterpret_cast<uintptr_t>(in + s) & 15);
   int64_t b0 = (int64_t)s - mis;
@@ -764,7 +765,7 @@ template <bool MONO, bool FUSED, bool CK>
 __global__ void __launch_bounds__(1024) k_count(WalkArgs a) {
   const Lds l = carve_lds(a.nrows);
   stage_tables(a, l, FUSED);
-  const Tables tb{lds_bytes_of(l.T), l.info, l.kind, a.sink, a.fail};
+  const Tables tb{lds_bytes_of(l.T), l.info, l.kind, a.sink, a.fail, 0};
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
   uint32_t cnt = 0, fail = kNone, nonempty = 0, big = 0;
   uint32_t s = 0, e = 0;
@@ -939,7 +940,7 @@ __global__ void __launch_bounds__(1024) k_emit(WalkArgs a) {
   if (j0 > first) return;  // the whole block lies after the first halted lane
   const Lds l = carve_lds(a.nrows);
   stage_tables(a, l, FUSED);
-  const Tables tb{lds_bytes_of(l.T), l.info, l.kind, a.sink, a.fail};
+  const Tables tb{lds_bytes_of(l.T), l.info, l.kind, a.sink, a.fail, 0};
   const uint32_t j = j0 + threadIdx.x;
   if (j >= a.nlanes || j > first) return;
   const uint64_t off = a.blk_sum[blockIdx.x] + a.lane_pre[j];
@@ -1119,7 +1120,7 @@ __global__ void __launch_bounds__(256) k_emit_win(WalkArgs a) {
   if (a.meta[0] != kNone || a.meta[1] != 0 || a.res->status != 0 || a.n == 0) return;
   const Lds l = carve_lds(a.nrows);
   stage_tables(a, l, false);
-  const Tables tb{lds_bytes_of(l.T), l.info, l.kind, a.sink, a.fail};
+  const Tables tb{lds_bytes_of(l.T), l.info, l.kind, a.sink, a.fail, 0};
   const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   uint32_t *stage = reinterpret_cast<uint32_t *>(l.ring) + wid * kStageWords;
   const uint32_t stage_addr = (uint32_t)(size_t)(lds_u32 *)stage;
@@ -1242,6 +1243,367 @@ __global__ void __launch_bounds__(256) k_emit_win(WalkArgs a) {
     cur = nxt;
     nxt = n2;
     dat = ndat;
+  }
+}
+
+
+// ------------------------------------------------------------- B. batched documents
+// Many documents, each with its own (lexer, mode) instance, in one sequence of launches
+// that a hipGraph can capture (fixed grids, no host synchronisation, work queues reset by
+// the first kernel).  The instances' packed tables are rebased into one combined table
+// (rows renumbered, so walk() and its absolute LDS addressing are unchanged) and all of
+// them sit in LDS.  Each document is split into lanes exactly as a single scan would split
+// it (Theorem 1, Theorem 3): lane jj of a document targets jj * lane_bytes inside it, and a
+// document whose useful map is empty, or that asks for a serial scan, is one lane.  Lanes
+// are numbered long single-lane documents first, so the longest walks start first; count
+// and emit workgroups pull 64-lane tiles from atomic queues (work stealing).  Each
+// document's result is its own scan's: its tokens up to and including its first halted
+// slice, error offset relative to the document.
+constexpr int kMaxInst = 8;
+
+struct BatchInst {
+  uint32_t start, sink, fail;  // row byte offsets in the combined table
+  uint32_t mono, refused;      // refused: empty useful map (one lane per document)
+  CertArg ca;
+};
+
+struct DocDev {  // mirrors lex_doc
+  uint64_t offset;
+  uint32_t length;
+  uint16_t inst, flags;
+};
+
+struct DocResDev {  // mirrors lex_doc_result
+  uint64_t tok_offset, ntokens, error_offset;
+  int32_t status;
+  uint32_t nslices;
+};
+
+enum { kQCount = 0, kQEmit = 1, kNLanes = 2, kBad = 3, kBatchMeta = 4 };
+
+struct BatchArgs {
+  const uint32_t *table;
+  const uint8_t *rowinfo, *rowkind, *luts;  // luts: ninst * 256 certificate bytes
+  int nrows;
+  uint32_t ninst;
+  BatchInst inst[kMaxInst];
+  const uint8_t *bytes;
+  uint64_t nbytes;
+  const DocDev *docs;
+  uint32_t ndocs, lane_bytes, max_lanes;
+  uint32_t *meta;  // kBatchMeta words: queues, lane count
+  uint32_t *lanes_of, *lane_base, *lane_doc, *cuts, *ends, *counts, *halted, *lane_pre, *doc_halt;
+  uint32_t *doc_ntok, *doc_nsl;
+  uint8_t *kinds;
+  uint32_t *lens;
+  uint64_t *offs;
+  uint64_t cap;
+  DocResDev *res;
+  ResultDev *total;
+};
+
+__host__ __device__ inline size_t batch_lds_offset(int nrows, uint32_t ninst) {
+  return align16((size_t)nrows * 1024 + 2 * (size_t)nrows + (size_t)ninst * 256);
+}
+
+struct BatchLds {
+  const lds_u8 *T;  // the combined table (LDS address 0)
+  const uint8_t *info, *kind, *luts;
+  uint8_t *ring;
+};
+
+// Stages the combined table (at LDS address 0), row info, kinds and LUTs.
+__device__ __forceinline__ BatchLds batch_stage(const BatchArgs &a) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const int words = a.nrows * 256;
+  const uint4 *src = reinterpret_cast<const uint4 *>(a.table);
+  uint4 *dst = reinterpret_cast<uint4 *>(smem);
+  for (int i = threadIdx.x; i < words / 4; i += blockDim.x) dst[i] = src[i];
+  uint8_t *info = smem + (size_t)a.nrows * 1024, *kind = info + a.nrows, *luts = kind + a.nrows;
+  for (int i = threadIdx.x; i < a.nrows; i += blockDim.x) {
+    info[i] = a.rowinfo[i];
+    kind[i] = a.rowkind[i];
+  }
+  for (uint32_t i = threadIdx.x; i < a.ninst * 256; i += blockDim.x) luts[i] = a.luts[i];
+  __syncthreads();
+  return BatchLds{lds_bytes_of(smem), info, kind, luts, smem + batch_lds_offset(a.nrows, a.ninst)};
+}
+
+__device__ __forceinline__ bool one_lane(const BatchArgs &a, const DocDev &d) {
+  // (an unknown instance stops the batch; it is never looked up)
+  return d.length <= a.lane_bytes || (d.flags & 1) || d.inst >= a.ninst || a.inst[d.inst].refused;
+}
+
+// One workgroup: lanes per document, lane numbering (long single-lane documents first),
+// queue reset.
+__global__ void __launch_bounds__(1024) k_bplan(BatchArgs a) {
+  __shared__ uint64_t part[1024];  // 64-bit: a hostile table may ask for more than 2^32 lanes
+  const uint32_t tid = threadIdx.x, nt = blockDim.x;
+  const uint32_t per = (a.ndocs + nt - 1) / nt;
+  const uint32_t lo = min(a.ndocs, tid * per), hi = min(a.ndocs, lo + per);
+  __shared__ uint32_t bad;
+  if (tid == 0) {
+    a.meta[kQCount] = 0;
+    a.meta[kQEmit] = 0;
+    bad = 0;
+  }
+  __syncthreads();
+  // the document table is the caller's device data: a document outside the bytes, an
+  // unknown instance or flag, or more lanes than the workspace holds stops the batch
+  for (uint32_t d = lo; d < hi; ++d) {
+    const DocDev doc = a.docs[d];
+    if (doc.offset > a.nbytes || doc.length > a.nbytes - doc.offset || doc.inst >= a.ninst || doc.flags > 1)
+      atomicOr(&bad, 1u);
+  }
+  uint64_t base = 0;
+  for (int group = 0; group < 2; ++group) {
+    uint64_t sum = 0;
+    for (uint32_t d = lo; d < hi; ++d) {
+      const DocDev doc = a.docs[d];
+      const uint32_t nl = one_lane(a, doc) ? 1 : (uint32_t)(((uint64_t)doc.length + a.lane_bytes - 1) / a.lane_bytes);
+      const bool first = nl == 1 && doc.length > a.lane_bytes;
+      if (group == 0) a.lanes_of[d] = nl;
+      if (first == (group == 0)) sum += nl;
+    }
+    part[tid] = sum;
+    __syncthreads();
+    for (uint32_t d = 1; d < nt; d <<= 1) {
+      const uint64_t v = tid >= d ? part[tid - d] : 0;
+      __syncthreads();
+      part[tid] += v;
+      __syncthreads();
+    }
+    uint64_t run = base + (tid ? part[tid - 1] : 0);
+    for (uint32_t d = lo; d < hi; ++d) {
+      const uint32_t nl = a.lanes_of[d];
+      const bool first = nl == 1 && a.docs[d].length > a.lane_bytes;
+      if (first == (group == 0)) {
+        a.lane_base[d] = (uint32_t)min<uint64_t>(run, 0xFFFFFFFFu);  // unused when stopped
+        run += nl;
+      }
+    }
+    base += part[nt - 1];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const bool stop = bad || base > a.max_lanes;
+    a.meta[kBad] = stop;
+    a.meta[kNLanes] = stop ? 0 : (uint32_t)base;
+  }
+}
+
+// A wave per document: the lane -> document map.
+__global__ void __launch_bounds__(256) k_bmap(BatchArgs a) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, nwaves = (gridDim.x * blockDim.x) >> 6;
+  if (a.meta[kBad]) return;
+  for (uint32_t d = wave; d < a.ndocs; d += nwaves) {
+    const uint32_t lb = a.lane_base[d], nl = a.lanes_of[d];
+    for (uint32_t k = lane; k < nl; k += 64) a.lane_doc[lb + k] = d;
+  }
+}
+
+// Pulls the next 64-lane tile for this wave (lane 0 takes it, the wave shares it).
+__device__ __forceinline__ uint32_t next_tile(uint32_t *q) {
+  uint32_t t = 0;
+  if ((threadIdx.x & 63) == 0) t = atomicAdd(q, 1u);
+  return (uint32_t)__shfl((int)t, 0);
+}
+
+// Count walk of the batch: each lane places its own slice inside its document (the fused
+// planner) and counts it with its document's table.
+__global__ void __launch_bounds__(256) k_bcount(BatchArgs a) {
+  const BatchLds l = batch_stage(a);
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t nlanes = a.meta[kNLanes];
+  for (;;) {
+    const uint32_t tile = next_tile(&a.meta[kQCount]);
+    if ((uint64_t)tile * 64 >= nlanes) break;  // wave-uniform exit
+    const uint32_t j = tile * 64 + lane;
+    const bool valid = j < nlanes;
+    uint32_t d = 0, jj = 0, nl = 1, start = kNone;
+    DocDev doc{0, 0, 0, 0};
+    if (valid) {
+      d = a.lane_doc[j];
+      doc = a.docs[d];
+      jj = j - a.lane_base[d];
+      nl = a.lanes_of[d];
+    }
+    const BatchInst &in = a.inst[valid ? doc.inst : 0];
+    const uint8_t *src = a.bytes + doc.offset;
+    const uint8_t *lut = l.luts + 256 * (valid ? doc.inst : 0);
+    if (valid) {
+      if (jj == 0) start = 0;
+      else start = search_cert(src, doc.length, in.ca, lut, jj * a.lane_bytes, a.lane_bytes, kNone);
+    }
+    // the next lane's start, when that lane is this document's and this tile's
+    const uint32_t nstart = (uint32_t)__shfl_down((int)start, 1);
+    if (!valid) continue;
+    const bool same = lane < 63 && jj + 1 < nl;
+    uint32_t s, e;
+    if (start == kNone) {
+      s = e = min(jj * a.lane_bytes, doc.length);
+    } else {
+      s = start;
+      if (jj + 1 == nl) e = doc.length;
+      else if (same && nstart != kNone) e = nstart;
+      else {
+        const uint32_t x1 = (jj + 1) * a.lane_bytes;
+        e = search_cert(src, doc.length, in.ca, lut, x1, doc.length - x1, doc.length);
+      }
+    }
+    a.cuts[j] = s;
+    a.ends[j] = e;
+    const Tables tb{l.T, l.info, l.kind, in.sink, in.fail, in.start};
+    LaneState L;
+    L.cnt = 0;
+    Ring r{};
+    const bool halted = in.mono ? walk<false, true, false>(L, r, tb, src, doc.length, s, e)
+                                : walk<false, false, false>(L, r, tb, src, doc.length, s, e);
+    a.counts[j] = L.cnt;
+    a.halted[j] = halted;
+  }
+}
+
+// A wave per document: its first halted lane, the token count up to and including it,
+// in-document prefixes of the lane counts, non-empty slices.
+__global__ void __launch_bounds__(256) k_bdoc(BatchArgs a) {
+  if (a.meta[kBad]) return;
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, nwaves = (gridDim.x * blockDim.x) >> 6;
+  for (uint32_t d = wave; d < a.ndocs; d += nwaves) {
+    const uint32_t lb = a.lane_base[d], nl = a.lanes_of[d];
+    uint32_t run = 0, nsl = 0, halt = kNone;
+    for (uint32_t c = 0; c < nl; c += 64) {
+      const bool ok = c + lane < nl;
+      const uint32_t j = lb + c + lane;
+      const uint32_t cnt = ok ? a.counts[j] : 0;
+      const bool h = ok && a.halted[j];
+      const bool ne = ok && a.cuts[j] < a.ends[j];
+      uint32_t incl = cnt;
+      for (int k = 1; k < 64; k <<= 1) {
+        const uint32_t v = (uint32_t)__shfl_up((int)incl, k);
+        if ((int)lane >= k) incl += v;
+      }
+      if (ok) a.lane_pre[j] = run + incl - cnt;
+      const unsigned long long hb = __ballot(h), nb = __ballot(ne);
+      if (hb) {  // wave-uniform
+        const int f = __ffsll(hb) - 1;
+        run += (uint32_t)__shfl((int)incl, f);
+        nsl += __popcll(nb & ((2ull << f) - 1));
+        halt = lb + c + f;
+        break;
+      }
+      run += (uint32_t)__shfl((int)incl, 63);
+      nsl += __popcll(nb);
+    }
+    if (lane == 0) {
+      a.doc_ntok[d] = run;
+      a.doc_halt[d] = halt;
+      a.doc_nsl[d] = nsl;
+    }
+  }
+}
+
+// One workgroup: output offsets of the documents (exclusive scan), results, status.
+__global__ void __launch_bounds__(1024) k_bscan(BatchArgs a) {
+  if (a.meta[kBad]) {  // nothing was counted: report the bad table
+    for (uint32_t d = threadIdx.x; d < a.ndocs; d += blockDim.x) a.res[d] = DocResDev{0, 0, 0, -1, 0};
+    if (threadIdx.x == 0) {
+      a.total->ntokens = 0;
+      a.total->error_offset = 0;
+      a.total->status = -1;
+      a.total->nslices = 0;
+    }
+    return;
+  }
+  __shared__ uint64_t part[1024];
+  __shared__ uint32_t perr[1024], pnsl[1024];
+  const uint32_t tid = threadIdx.x, nt = blockDim.x;
+  const uint32_t per = (a.ndocs + nt - 1) / nt;
+  const uint32_t lo = min(a.ndocs, tid * per), hi = min(a.ndocs, lo + per);
+  uint64_t sum = 0;
+  uint32_t nerr = 0, nsl = 0;
+  for (uint32_t d = lo; d < hi; ++d) {
+    sum += a.doc_ntok[d];
+    nerr += a.doc_halt[d] != kNone;
+    nsl += a.doc_nsl[d];
+  }
+  part[tid] = sum;
+  perr[tid] = nerr;
+  pnsl[tid] = nsl;
+  __syncthreads();
+  for (uint32_t k = 1; k < nt; k <<= 1) {
+    const uint64_t v = tid >= k ? part[tid - k] : 0;
+    const uint32_t ve = tid >= k ? perr[tid - k] : 0, vn = tid >= k ? pnsl[tid - k] : 0;
+    __syncthreads();
+    part[tid] += v;
+    perr[tid] += ve;
+    pnsl[tid] += vn;
+    __syncthreads();
+  }
+  const uint64_t total = part[nt - 1];
+  const int32_t status = total > a.cap ? -4 : 0;
+  uint64_t run = tid ? part[tid - 1] : 0;
+  for (uint32_t d = lo; d < hi; ++d) {
+    DocResDev r;
+    r.tok_offset = run;
+    r.ntokens = a.doc_ntok[d];
+    r.error_offset = a.docs[d].length;  // a halted document's emit replaces it
+    r.status = status;
+    r.nslices = a.doc_nsl[d];
+    a.res[d] = r;
+    run += r.ntokens;
+  }
+  if (tid == 0) {
+    a.total->ntokens = total;
+    a.total->error_offset = perr[nt - 1];  // documents that did not tokenize completely
+    a.total->status = status;
+    a.total->nslices = pnsl[nt - 1];
+  }
+}
+
+// Emit walk of the batch: the lane emit of each lane up to its document's first halted one.
+__global__ void __launch_bounds__(256) k_bemit(BatchArgs a) {
+  const BatchLds l = batch_stage(a);
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t nlanes = a.meta[kNLanes];
+  const bool write = a.total->status == 0;
+  for (;;) {
+    const uint32_t tile = next_tile(&a.meta[kQEmit]);
+    if ((uint64_t)tile * 64 >= nlanes) break;  // wave-uniform exit
+    const uint32_t j = tile * 64 + lane;
+    if (j >= nlanes) continue;
+    const uint32_t d = a.lane_doc[j];
+    const uint32_t halt = a.doc_halt[d];
+    if (halt != kNone && j > halt) continue;
+    const DocDev doc = a.docs[d];
+    const BatchInst &in = a.inst[doc.inst];
+    const uint8_t *src = a.bytes + doc.offset;
+    const uint32_t s = a.cuts[j], e = a.ends[j];
+    const uint32_t off = (uint32_t)a.res[d].tok_offset + a.lane_pre[j];
+    Ring r;
+    r.w = reinterpret_cast<uint32_t *>(l.ring) + threadIdx.x;
+    r.stride = blockDim.x;
+    r.kinds = a.kinds;
+    r.lens = a.lens;
+    r.offs = a.offs;
+    r.o = off;
+    r.fl = off & ~(uint32_t)(kChunk - 1);
+    r.first = off;
+    r.write = write;
+    r.direct = e - s >= (1u << 24);
+    const Tables tb{l.T, l.info, l.kind, in.sink, in.fail, in.start};
+    LaneState L;
+    L.cnt = 0;
+    if (in.mono) {
+      if (!r.direct && !r.offs) walk<true, true, true>(L, r, tb, src, doc.length, s, e);
+      else walk<true, true, false>(L, r, tb, src, doc.length, s, e);
+    } else {
+      walk<true, false, false>(L, r, tb, src, doc.length, s, e);
+    }
+    ring_flush_tail(r);
+    if (j == halt) a.res[d].error_offset = L.tok;  // the halt offset, relative to the document
   }
 }
 
@@ -1476,6 +1838,108 @@ hipError_t run_pipeline(const DevTable &t, const CertMap &cm, const uint8_t *in,
   if (e != hipSuccess) return e;
   const WalkArgs a = walk_args(t, cm, in, p, kinds, lens, offs, cap, res, nullptr);
   return count_scan_emit<false>(t, a, p, cap, res, s, ev);
+}
+
+// ------------------------------------------------------------------ batches
+static uint32_t batch_max_lanes(uint32_t ndocs, uint64_t nbytes, uint32_t lane_bytes) {
+  return (uint32_t)std::min<uint64_t>(0xFFFFFFF0ull, (uint64_t)ndocs + nbytes / lane_bytes + 1);
+}
+
+size_t batch_workspace_bytes(uint32_t ndocs, uint64_t nbytes, uint32_t lane_bytes) {
+  const uint64_t nl = batch_max_lanes(ndocs, nbytes, lane_bytes);
+  return align256(kBatchMeta * 4) + 5 * align256((size_t)std::max<uint32_t>(ndocs, 1) * 4) +
+         6 * align256((size_t)nl * 4);
+}
+
+size_t batch_emit_lds_bytes(int nrows, uint32_t ninst) {
+  const size_t b = batch_lds_offset(nrows, ninst) + 256 * (size_t)kRingBytes;
+  return b <= 160 * 1024 ? b : 0;
+}
+
+hipError_t run_batch(const BatchTables &bt, const uint8_t *bytes, uint64_t nbytes, const void *docs, uint32_t ndocs,
+                     uint32_t lane_bytes, uint8_t *kinds, uint32_t *lens, uint64_t *offs, uint64_t cap, void *res,
+                     ResultDev *total, void *ws, size_t ws_bytes, hipStream_t s, hipEvent_t const *ev) {
+  if (ws_bytes < batch_workspace_bytes(ndocs, nbytes, lane_bytes)) return hipErrorInvalidValue;
+  const size_t lds_e = batch_emit_lds_bytes(bt.nrows, bt.ninst);
+  if (!lds_e || bt.ninst == 0 || bt.ninst > (uint32_t)kMaxInst) return hipErrorInvalidValue;
+  BatchArgs a{};
+  a.table = bt.table;
+  a.rowinfo = bt.rowinfo;
+  a.rowkind = bt.rowkind;
+  a.luts = bt.luts;
+  a.nrows = bt.nrows;
+  a.ninst = bt.ninst;
+  for (uint32_t k = 0; k < bt.ninst; ++k) {
+    a.inst[k].start = bt.inst[k].start;
+    a.inst[k].sink = bt.inst[k].sink;
+    a.inst[k].fail = bt.inst[k].fail;
+    a.inst[k].mono = bt.inst[k].mono;
+    a.inst[k].refused = bt.inst[k].refused;
+    a.inst[k].ca = cert_arg(bt.inst[k].cm);
+  }
+  a.bytes = bytes;
+  a.nbytes = nbytes;
+  a.docs = static_cast<const DocDev *>(docs);
+  a.ndocs = ndocs;
+  a.lane_bytes = lane_bytes;
+  a.max_lanes = batch_max_lanes(ndocs, nbytes, lane_bytes);
+  // workspace: the per-lane arrays are sized for the most lanes the byte count allows
+  uint8_t *w = static_cast<uint8_t *>(ws);
+  a.meta = reinterpret_cast<uint32_t *>(w);
+  w += align256(kBatchMeta * 4);
+  const size_t dsz = align256((size_t)std::max<uint32_t>(ndocs, 1) * 4);
+  a.lanes_of = reinterpret_cast<uint32_t *>(w), w += dsz;
+  a.lane_base = reinterpret_cast<uint32_t *>(w), w += dsz;
+  a.doc_halt = reinterpret_cast<uint32_t *>(w), w += dsz;
+  a.doc_ntok = reinterpret_cast<uint32_t *>(w), w += dsz;
+  a.doc_nsl = reinterpret_cast<uint32_t *>(w), w += dsz;
+  const size_t per_lane = align256((size_t)batch_max_lanes(ndocs, nbytes, lane_bytes) * 4);
+  a.lane_doc = reinterpret_cast<uint32_t *>(w), w += per_lane;
+  a.cuts = reinterpret_cast<uint32_t *>(w), w += per_lane;
+  a.ends = reinterpret_cast<uint32_t *>(w), w += per_lane;
+  a.counts = reinterpret_cast<uint32_t *>(w), w += per_lane;
+  a.halted = reinterpret_cast<uint32_t *>(w), w += per_lane;
+  a.lane_pre = reinterpret_cast<uint32_t *>(w), w += per_lane;
+  a.kinds = kinds;
+  a.lens = lens;
+  a.offs = offs;
+  a.cap = cap;
+  a.res = static_cast<DocResDev *>(res);
+  a.total = total;
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  const size_t lds_c = batch_lds_offset(bt.nrows, bt.ninst);
+  const uint32_t per_cu_c = (uint32_t)std::min<size_t>(8, 160 * 1024 / lds_c);
+  const uint32_t per_cu_e = (uint32_t)std::min<size_t>(8, 160 * 1024 / lds_e);
+  const uint32_t gdoc = std::max<uint32_t>(1, std::min<uint32_t>(4096, (ndocs + 3) / 4));
+  mark(ev, 0, s);
+  k_bplan<<<1, 1024, 0, s>>>(a);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) {
+    k_bmap<<<gdoc, 256, 0, s>>>(a);
+    e = hipGetLastError();
+  }
+  mark(ev, 1, s);
+  if (e == hipSuccess) {
+    k_bcount<<<(uint32_t)cus * per_cu_c, 256, lds_c, s>>>(a);
+    e = hipGetLastError();
+  }
+  mark(ev, 2, s);
+  if (e == hipSuccess) {
+    k_bdoc<<<gdoc, 256, 0, s>>>(a);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) {
+    k_bscan<<<1, 1024, 0, s>>>(a);
+    e = hipGetLastError();
+  }
+  mark(ev, 3, s);
+  if (e == hipSuccess) {
+    k_bemit<<<(uint32_t)cus * per_cu_e, 256, lds_e, s>>>(a);
+    e = hipGetLastError();
+  }
+  mark(ev, 4, s);
+  return e;
 }
 
 hipError_t run_fused(const DevTable &t, const CertMap &cm, const uint8_t *cert_lut, const uint8_t *in,

@@ -26,6 +26,11 @@ struct DevCopy {
   uint8_t *d_cert_lut[2] = {nullptr, nullptr};  // 256-byte 0/1 useful maps
 };
 
+struct lex_batch {
+  int device = -1;
+  lexk::BatchTables bt{};
+};
+
 struct lex_dfa {
   lexc::Compiled c;
   lexk::CertMap cm[2];
@@ -309,6 +314,131 @@ int lex_run(const lex_dfa *d, const uint8_t *d_bytes, uint64_t n, int mode, uint
                                                   cap, res, s, ev)
                              : lexk::run_fused(t, d->cm[m], dc->d_cert_lut[m], d_bytes, p, r.serial, d_kinds,
                                                d_lens, d_offsets, cap, res, s, ev);
+  return e == hipSuccess ? LEX_OK : LEX_EDEVICE;
+}
+
+int lex_batch_create(const lex_dfa *const *dfas, const int32_t *modes, uint32_t ninst, lex_batch **out, char *err,
+                     size_t errlen) {
+  if (!dfas || !modes || !out || ninst == 0) {
+    set_err(err, errlen, "null argument or no instances");
+    return LEX_EINVAL;
+  }
+  *out = nullptr;
+  if (ninst > (uint32_t)lexk::kBatchMaxInst) {
+    set_err(err, errlen, "at most 8 instances");
+    return LEX_ELIMIT;
+  }
+  int total_rows = 0;
+  for (uint32_t k = 0; k < ninst; ++k) {
+    if (!dfas[k] || (modes[k] != LEX_MODE_EXACT && modes[k] != LEX_MODE_DISCARD)) {
+      set_err(err, errlen, "bad instance " + std::to_string(k));
+      return LEX_EINVAL;
+    }
+    total_rows += dfas[k]->c.nrows;
+  }
+  if (total_rows >= lexc::kMaxRows || lexk::batch_emit_lds_bytes(total_rows, ninst) == 0) {
+    set_err(err, errlen, "combined tables too large for LDS (" + std::to_string(total_rows) + " rows)");
+    return LEX_ELIMIT;
+  }
+  // Rebase every instance's packed table into one: rows of instance k follow those of the
+  // earlier instances; each entry's next-row field and swizzle are renumbered, and each
+  // row's columns are re-permuted for its new swizzle.
+  std::vector<uint32_t> table((size_t)total_rows * 256);
+  std::vector<uint8_t> info(total_rows), kind(total_rows), luts((size_t)ninst * 256);
+  lexk::BatchTables bt{};
+  bt.nrows = total_rows;
+  bt.ninst = ninst;
+  auto state = [](uint32_t row) { return (row << lexc::kRowShift) | (lexc::row_swizzle((int)row) << 2); };
+  uint32_t base = 0;
+  for (uint32_t k = 0; k < ninst; ++k) {
+    const lexc::Compiled &c = dfas[k]->c;
+    const int m = modes[k];
+    for (int r = 0; r < c.nrows; ++r) {
+      const uint32_t nr = base + (uint32_t)r;
+      for (int b = 0; b < 256; ++b) {
+        const uint32_t e = c.table[m][(size_t)r * 256 + ((uint32_t)b ^ lexc::row_swizzle(r))];
+        const uint32_t next = (e & lexc::kStateMask) >> lexc::kRowShift;
+        const uint32_t flags = e & ~lexc::kStateMask;
+        table[(size_t)nr * 256 + ((uint32_t)b ^ lexc::row_swizzle((int)nr))] = flags | state(base + next);
+      }
+      info[nr] = c.rowinfo[m][r];
+      kind[nr] = c.rowkind[r];
+    }
+    memcpy(&luts[(size_t)k * 256], dfas[k]->lut[m].data(), 256);
+    lexk::BatchInstHost &in = bt.inst[k];
+    in.start = state(base);
+    in.sink = state(base + (uint32_t)c.row_sink);
+    in.fail = c.row_fail >= 0 ? state(base + (uint32_t)c.row_fail) : in.sink;
+    in.mono = c.monotone ? 1 : 0;
+    in.refused = dfas[k]->cm[m].nbytes == 0;
+    in.cm = dfas[k]->cm[m];
+    base += (uint32_t)c.nrows;
+  }
+  lex_batch *bb = new lex_batch;
+  (void)hipGetDevice(&bb->device);
+  uint32_t *d_table = nullptr;
+  uint8_t *d_info = nullptr, *d_kind = nullptr, *d_luts = nullptr;
+  hipError_t e = upload(&d_table, table.data(), table.size());
+  if (e == hipSuccess) e = upload(&d_info, info.data(), info.size());
+  if (e == hipSuccess) e = upload(&d_kind, kind.data(), kind.size());
+  if (e == hipSuccess) e = upload(&d_luts, luts.data(), luts.size());
+  bt.table = d_table;
+  bt.rowinfo = d_info;
+  bt.rowkind = d_kind;
+  bt.luts = d_luts;
+  bb->bt = bt;
+  if (e != hipSuccess) {
+    lex_batch_free(bb);
+    set_err(err, errlen, "device upload failed");
+    return LEX_EDEVICE;
+  }
+  *out = bb;
+  return LEX_OK;
+}
+
+void lex_batch_free(lex_batch *b) {
+  if (!b) return;
+  int cur = -1;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(b->device);
+  if (b->bt.table) (void)hipFree(const_cast<uint32_t *>(b->bt.table));
+  if (b->bt.rowinfo) (void)hipFree(const_cast<uint8_t *>(b->bt.rowinfo));
+  if (b->bt.rowkind) (void)hipFree(const_cast<uint8_t *>(b->bt.rowkind));
+  if (b->bt.luts) (void)hipFree(const_cast<uint8_t *>(b->bt.luts));
+  if (cur >= 0) (void)hipSetDevice(cur);
+  delete b;
+}
+
+static int batch_lane_bytes(const lex_run_opts *o, uint32_t &lb) {
+  lb = o && o->lane_bytes ? o->lane_bytes : 1024u;
+  if (lb < 16 || (lb & 15)) return LEX_EINVAL;
+  if (o && (o->emit || (o->path && o->path != 2))) return LEX_EINVAL;  // the batch plans like path 2
+  return LEX_OK;
+}
+
+size_t lex_batch_workspace_size(const lex_batch *b, uint32_t ndocs, uint64_t nbytes, const lex_run_opts *opts) {
+  uint32_t lb = 0;
+  if (!b || nbytes > 0xFFFFFFF0ull || batch_lane_bytes(opts, lb) != LEX_OK) return 0;
+  return lexk::batch_workspace_bytes(ndocs, nbytes, lb);
+}
+
+int lex_run_batch(const lex_batch *b, const uint8_t *d_bytes, uint64_t nbytes, const lex_doc *d_docs, uint32_t ndocs,
+                  uint8_t *d_kinds, uint32_t *d_lens, uint64_t *d_offsets, uint64_t cap, lex_doc_result *d_res,
+                  lex_result *d_total, void *d_ws, size_t ws_bytes, const lex_run_opts *opts, void *stream) {
+  if (!b || !d_total || !d_ws || (ndocs && (!d_docs || !d_res)) || (!d_bytes && nbytes)) return LEX_EINVAL;
+  if (cap && (!d_kinds || !d_lens)) return LEX_EINVAL;
+  if ((reinterpret_cast<uintptr_t>(d_kinds) | reinterpret_cast<uintptr_t>(d_lens)) & 15) return LEX_EINVAL;
+  if (nbytes > 0xFFFFFFF0ull || cap > 0xFFFFFFF0ull) return LEX_ELIMIT;
+  uint32_t lb = 0;
+  int rc = batch_lane_bytes(opts, lb);
+  if (rc != LEX_OK) return rc;
+  if (ws_bytes < lexk::batch_workspace_bytes(ndocs, nbytes, lb)) return LEX_ELIMIT;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev != b->device) return LEX_EDEVICE;
+  hipEvent_t const *ev = opts && opts->events ? reinterpret_cast<hipEvent_t const *>(opts->events) : nullptr;
+  hipError_t e = lexk::run_batch(b->bt, d_bytes, nbytes, d_docs, ndocs, lb, d_kinds, d_lens, d_offsets, cap, d_res,
+                                 reinterpret_cast<lexk::ResultDev *>(d_total), d_ws, ws_bytes,
+                                 static_cast<hipStream_t>(stream), ev);
   return e == hipSuccess ? LEX_OK : LEX_EDEVICE;
 }
 

@@ -175,3 +175,87 @@ class Lexer:
         abi.check(abi.lib().lex_cert_bitmap(self._h, data.data_ptr() if n else None, n, mode,
                                             bits.data_ptr(), C.c_void_p(s.cuda_stream)))
         return bits
+
+
+@dataclass
+class BatchResult:
+    kinds: "object"       # torch.uint8 [ntokens] (device)
+    lens: "object"        # torch.int32 [ntokens] (device), u32 values
+    offsets: "object"     # torch.int64 [ntokens] (device, relative to each document) or None
+    docs: "object"        # numpy structured array: tok_offset, ntokens, error_offset, status, nslices
+    ntokens: int
+    nerrors: int          # documents that did not tokenize completely
+    status: int
+    nslices: int
+
+
+DOC_DTYPE = np.dtype([("offset", "<u8"), ("length", "<u4"), ("inst", "<u2"), ("flags", "<u2")])
+DOC_RESULT_DTYPE = np.dtype([("tok_offset", "<u8"), ("ntokens", "<u8"), ("error_offset", "<u8"),
+                             ("status", "<i4"), ("nslices", "<u4")])
+
+
+class Batch:
+    """Several (lexer, mode) instances resident together for batched document scans
+    (lex_batch).  Documents are described by DOC_DTYPE records."""
+
+    def __init__(self, instances):
+        """instances: [(Lexer, mode), ...] (at most 8)."""
+        L = abi.lib()
+        self._keep = [lx for lx, _ in instances]
+        hs = (C.c_void_p * len(instances))(*[lx._h for lx, _ in instances])
+        ms = (C.c_int32 * len(instances))(*[int(m) for _, m in instances])
+        out = C.c_void_p()
+        err = C.create_string_buffer(512)
+        abi.check(L.lex_batch_create(hs, ms, len(instances), C.byref(out), err, 512), err.value.decode())
+        self._h = out.value
+
+    def __del__(self):
+        h, self._h = getattr(self, "_h", None), None
+        if h:
+            try:
+                abi.lib().lex_batch_free(h)
+            except Exception:
+                pass
+
+    def workspace_size(self, ndocs: int, nbytes: int, opts: abi.RunOpts | None = None) -> int:
+        return abi.lib().lex_batch_workspace_size(self._h, ndocs, nbytes, C.byref(opts) if opts else None)
+
+    def run_into(self, data, nbytes, docs_dev, ndocs, kinds, lens, offsets, cap, res_dev, total_dev, ws,
+                 opts: abi.RunOpts | None = None, stream=None):
+        """Enqueues one batched scan on `stream` (torch stream; default: current); device
+        tensors throughout.  Capturable in a CUDA graph."""
+        import torch
+
+        s = stream if stream is not None else torch.cuda.current_stream()
+        abi.check(abi.lib().lex_run_batch(
+            self._h, data.data_ptr() if nbytes else None, nbytes, docs_dev.data_ptr() if ndocs else None,
+            ndocs, kinds.data_ptr(), lens.data_ptr(), offsets.data_ptr() if offsets is not None else None,
+            cap, res_dev.data_ptr() if ndocs else None, total_dev.data_ptr(), ws.data_ptr(), ws.numel(),
+            C.byref(opts) if opts else None, C.c_void_p(s.cuda_stream)))
+
+    def run(self, data, docs: np.ndarray, offsets: bool = False, cap: int | None = None,
+            opts: abi.RunOpts | None = None) -> BatchResult:
+        """Scans the documents `docs` (DOC_DTYPE records) of the uint8 CUDA tensor `data`."""
+        import torch
+
+        dev = data.device
+        n = data.numel()
+        docs = np.ascontiguousarray(docs, dtype=DOC_DTYPE)
+        nd = docs.size
+        cap = n if cap is None else cap
+        docs_dev = torch.from_numpy(docs.view(np.uint8).copy()).to(dev)
+        kinds = torch.empty(max(cap, 1), dtype=torch.uint8, device=dev)
+        lens = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+        offs = torch.empty(max(cap, 1), dtype=torch.int64, device=dev) if offsets else None
+        res = torch.empty(max(nd, 1) * 32, dtype=torch.uint8, device=dev)
+        total = torch.zeros(3, dtype=torch.int64, device=dev)
+        ws = torch.empty(self.workspace_size(nd, n, opts), dtype=torch.uint8, device=dev)
+        self.run_into(data, n, docs_dev, nd, kinds, lens, offs, cap, res, total, ws, opts)
+        t = total.cpu().numpy()
+        per = res.cpu().numpy()[: nd * 32].view(DOC_RESULT_DTYPE)
+        ntok, nerr = int(t[0]), int(t[1])
+        status = int(np.int32(t[2] & 0xFFFFFFFF))
+        nsl = int((int(t[2]) >> 32) & 0xFFFFFFFF)
+        k = min(ntok, cap) if status == 0 else 0
+        return BatchResult(kinds[:k], lens[:k], offs[:k] if offs is not None else None, per, ntok, nerr,
+                           status, nsl)

@@ -61,3 +61,21 @@ def test_info_and_tables():
     assert int(((t & 0x00FFFC00) >> 10).max()) < info["nrows"]
     # the swizzle field matches the next row
     assert np.array_equal((t >> 2) & 31, ((t >> 10) & 0x3FFF) & 31)
+
+
+def test_batch_argument_checks():
+    """lex_batch_create validates on the host before touching a device."""
+    L = P.lib()
+    lx = P.Lexer.compile(T.as_tuples(T.CLIKE_L))
+    out = C.c_void_p()
+    err = C.create_string_buffer(256)
+    hs = (C.c_void_p * 9)(*([lx._h] * 9))
+    ms = (C.c_int32 * 9)(*([0] * 9))
+    assert L.lex_batch_create(None, ms, 1, C.byref(out), err, 256) == P.LEX_EINVAL
+    assert L.lex_batch_create(hs, ms, 0, C.byref(out), err, 256) == P.LEX_EINVAL
+    assert L.lex_batch_create(hs, ms, 9, C.byref(out), err, 256) == P.LEX_ELIMIT
+    bad = (C.c_int32 * 1)(2)  # serial is a per-document flag, not an instance mode
+    assert L.lex_batch_create(hs, bad, 1, C.byref(out), err, 256) == P.LEX_EINVAL
+    assert L.lex_batch_workspace_size(None, 10, 1000, None) == 0
+    assert L.lex_run_batch(None, None, 0, None, 0, None, None, None, 0, None, None, None, 0, None, None) == P.LEX_EINVAL
+    assert np.dtype(P.DOC_DTYPE).itemsize == 16 and np.dtype(P.DOC_RESULT_DTYPE).itemsize == 32
