@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-documents leg")
     ap.add_argument("--batch-docs", type=int, default=50000)
     ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-seconds", type=float, default=4.0, help="per arrival rate (plus 1 s warm-up)")
     ap.add_argument("--copy-ref", action="store_true",
                     help="also run one plain device copy of n bytes (scale for HBM counters)")
     return ap.parse_args()
@@ -151,6 +153,9 @@ def main():
         del data, kinds, lens, ws
         torch.cuda.empty_cache()
         out["batched"] = batched_leg(args)
+    if not args.no_serving:
+        torch.cuda.empty_cache()
+        out["serving"] = serving_leg(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(host, args)
     print(json.dumps(out), flush=True)
@@ -229,6 +234,25 @@ def batched_leg(args):
         "speedup": round(t_plain / t_batch, 2), "same_token_counts": same,
         "refused_docs": int((sets == workloads.DOC_B).sum()),
     }
+
+
+def serving_leg(args):
+    """The serving workload: open-loop Poisson arrivals at 2k, 10k and 50k requests/s,
+    requests of log-normal size (median 8 KiB, sigma 1.5, 64 B - 4 MiB) drawn from a pool of
+    3 x 2048 documents (C-like-L exact, C-like-D discard, JSON discard), 16 GiB HBM budget,
+    four slots; p50/p99 latency from arrival to result in pinned host memory.  Each rate
+    runs --serve-seconds after a 1 s warm-up (the paper-scale run is 60 s per rate:
+    python -m paper_2608_03473_amd.serve)."""
+    from paper_2608_03473_amd import serve
+
+    pool = serve.make_pool(2048, 7)
+    server = serve.Server(serve.instances(), budget_bytes=16 << 30, slots=4)
+    out = []
+    for rate in (2000.0, 10000.0, 50000.0):
+        m = serve.open_loop(server, pool, rate, args.serve_seconds + 1.0, 6, warmup=1.0)
+        log(args, f"serving {rate:.0f}/s: {m}")
+        out.append(m)
+    return out
 
 
 def measured_traffic(kernel, n, lane_bytes, path):
