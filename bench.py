@@ -20,7 +20,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2608_03473_amd", "csrc", "kernels.hip")
-HBM_SUMMARY = os.path.join(ROOT, "profiles", "walk_kernels_clike512_hbm.md")
+HBM_SUMMARY = os.path.join(ROOT, "profiles", "onepass_clike512_hbm.md")
 
 
 def parse():
@@ -113,8 +113,15 @@ def main():
         sys.exit(1)
     phases = np.array([e.elapsed_ms() for e in evs])  # steps x 4
     ph_mean = phases.mean(axis=0)
-    names = ["plan", "count_walk", "scan", "emit_walk"]
-    algo = {"plan": n + n / 8, "count_walk": n, "scan": 0, "emit_walk": n + 5 * ntok}
+    plan = lx.plan(n, mode, opts)
+    if plan["path"] == 3:
+        # one pass: reset, the one-pass kernel (plan, count walk, look-back, windowed emit),
+        # scan, and the lane emit's fallback (it returns at once on a clean scan)
+        names = ["reset", "onepass", "scan", "fallback_emit"]
+        algo = {"reset": 0, "onepass": n + 5 * ntok, "scan": 0, "fallback_emit": 0}
+    else:
+        names = ["plan", "count_walk", "scan", "emit_walk"]
+        algo = {"plan": n + n / 8, "count_walk": n, "scan": 0, "emit_walk": n + 5 * ntok}
     dom = names[int(np.argmax(ph_mean))]
     achieved = algo[dom] / (ph_mean[names.index(dom)] * 1e-3) / 1e9
     gbs = n / (ms * 1e-3) / 1e9
@@ -136,7 +143,8 @@ def main():
             "workload": f"C-like-L exact mode, {n} B C-like corpus (seed {args.seed}), "
                         f"{args.chunk_bytes} B chunks",
             "n_bytes": n, "tokens": ntok, "bytes_per_token": round(n / ntok, 3),
-            "slices": nslices, "lane_bytes": args.lane_bytes or "auto", "path": args.path or "default",
+            "slices": nslices, "lane_bytes": plan["lane_bytes"], "path": plan["path"],
+            "block_threads": plan["block_threads"],
         },
         "tokens_per_s": round(ntok / (ms * 1e-3), 1),
         "path_roofline_frac": round(path_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
@@ -166,7 +174,9 @@ def batched_leg(args):
     sigma 1.5, 64 B - 8 MiB), C-like-L exact .475 / C-like-D discard .475 / C-like-B discard
     .05 (refused: one slice each).  One batched scan (lex_run_batch: one launch sequence,
     work-stealing tiles) against one lex_run per document, same library, same bytes in HBM,
-    outputs and workspaces preallocated.  Both must give the same token counts."""
+    outputs and workspaces preallocated, on one stream and round-robin over four.  All must
+    give the same token counts.  Also reported: the critical path, the largest refused
+    document scanned alone."""
     import numpy as np
     import torch
 
@@ -225,14 +235,55 @@ def batched_leg(args):
     t_plain = time.perf_counter() - t
     ntok_plain = int(ores[:, 0].sum().item())
     same = ntok_plain == ntok_batch and bool((ores[:, 0].cpu().numpy() == per["ntokens"]).all())
+    # the same per-document launches spread round-robin over four streams, each with its own
+    # outputs and workspaces
+    streams = [torch.cuda.Stream(device=dev) for _ in range(4)]
+    sk = [torch.empty(cap, dtype=torch.uint8, device=dev) for _ in streams]
+    sl = [torch.empty(cap, dtype=torch.int32, device=dev) for _ in streams]
+    sws = [[torch.empty(lx.workspace_size(cap, m), dtype=torch.uint8, device=dev) for lx, (_, m) in zip(lexers, insts)]
+           for _ in streams]
+    ores4 = torch.zeros((nd, 3), dtype=torch.int64, device=dev)
+
+    def plain4():
+        for i in range(nd):
+            k, q = int(sets[i]), i & 3
+            lexers[k].run_into(views[i], int(sizes[i]), insts[k][1], sk[q], sl[q], None, cap, ores4[i], sws[q][k],
+                               None, streams[q])
+
+    torch.cuda.synchronize()
+    plain4()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    plain4()
+    torch.cuda.synchronize()
+    t_plain4 = time.perf_counter() - t
+    same = same and bool(torch.equal(ores4[:, 0], ores[:, 0]))
+    # the critical path: the largest refused document, scanned alone (one lane)
+    refused = np.flatnonzero(sets == workloads.DOC_B)
+    crit = {}
+    if refused.size:
+        i = int(refused[np.argmax(sizes[refused])])
+        k = int(sets[i])
+        reps = 3
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            lexers[k].run_into(views[i], int(sizes[i]), insts[k][1], okinds, olens, None, cap, ores[i], wss[k], None,
+                               stream)
+        torch.cuda.synchronize()
+        t_crit = (time.perf_counter() - t) / reps
+        crit = {"critical_doc_bytes": int(sizes[i]), "critical_doc_ms": round(t_crit * 1e3, 3),
+                "critical_doc_mbs": round(int(sizes[i]) / t_crit / 1e6, 1)}
     return {
         "workload": f"{nd} documents, log-normal sizes (median 16 KiB, sigma 1.5, 64 B - 8 MiB), seed 5; "
                     "C-like-L exact / C-like-D discard / C-like-B discard (refused) = .475/.475/.05",
         "bytes": n, "tokens": ntok_batch,
         "batched_gbs": round(n / t_batch / 1e9, 3), "batched_ms": round(t_batch * 1e3, 3),
         "plain_gbs": round(n / t_plain / 1e9, 3), "plain_ms": round(t_plain * 1e3, 3),
-        "speedup": round(t_plain / t_batch, 2), "same_token_counts": same,
-        "refused_docs": int((sets == workloads.DOC_B).sum()),
+        "speedup": round(t_plain / t_batch, 2),
+        "plain_4streams_ms": round(t_plain4 * 1e3, 3), "speedup_vs_4streams": round(t_plain4 / t_batch, 2),
+        "same_token_counts": same,
+        "refused_docs": int((sets == workloads.DOC_B).sum()), **crit,
     }
 
 
@@ -255,15 +306,24 @@ def serving_leg(args):
     return out
 
 
+def code_digest(path):
+    """SHA-256 of a C/HIP source with its comments and whitespace removed: the counters of a
+    kernel stay valid across edits of its comments, not across edits of its code."""
+    import hashlib
+    import re
+
+    src = open(path, encoding="utf-8").read()
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    return hashlib.sha256(" ".join(src.split()).encode()).hexdigest()
+
+
 def measured_traffic(kernel, n, lane_bytes, path):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary
     (FETCH_SIZE and WRITE_SIZE, scaled against a plain copy), or None when the summary was
-    taken on another kernel source or another workload."""
-    import hashlib
-
+    taken on other kernel code or another workload."""
     try:
-        with open(KERNEL_SOURCE, "rb") as f:
-            sha = hashlib.sha256(f.read()).hexdigest()
+        sha = code_digest(KERNEL_SOURCE)
         fields = {}
         with open(HBM_SUMMARY) as f:
             for line in f:
@@ -272,7 +332,7 @@ def measured_traffic(kernel, n, lane_bytes, path):
                     fields[k.strip()] = v.strip()
     except OSError:
         return None
-    if fields.get("kernels_hip_sha256") != sha:
+    if fields.get("kernels_hip_code_sha256") != sha:
         return None
     if fields.get("workload_n") != str(n) or fields.get("lane_bytes") != str(lane_bytes or "auto") \
             or fields.get("path") != str(path or "default"):

@@ -123,19 +123,25 @@ int lex_tables(const lex_dfa *dfa, int mode, uint32_t *table, size_t table_entri
 /* Tuning of one scan (NULL = defaults).  chunk_bytes: target length of the paper's
  * equal-division chunks (boundaries slide forward to the next certified byte); lane_bytes:
  * target length of the sub-slices one GPU lane walks (a multiple of 16 and a divisor of
- * chunk_bytes; 0 = chosen from n).  path: 0 = default (fused), 1 = the five-step
- * pipeline (bitmap, plan, count walk, scan, emit walk), 2 = fused (each lane finds its own
- * cut, no bitmap).  block_threads: threads per walk workgroup, 256, 512 or 1024 (0 = the
- * largest whose LDS fits).  emit: 0 = default, 1 = lane emit only.  By default a scan
- * whose automaton is monotone (no live edge from an accepting to a non-accepting state),
- * counts every token end in its mode (exact mode, or no discarded kind) and has at most
- * 256 rows uses the windowed emit: the count walk records checkpoints every 64 bytes
- * and the emit walk runs one thread per 64-byte sub-slice; a scan with a halted slice or
- * a slice of 2^24 bytes or more falls back to the lane emit (one thread per slice) on the
- * device.  Both write the same outputs.  events: optional array of LEX_NPHASES + 1
- * hipEvent_t (passed as void*, created by the caller) recorded on the scan's stream at
- * the phase boundaries: [0] start, [1] after planning (steps a, b), [2] after the count
- * walk (c), [3] after the scan (d), [4] after the emit walk (e). */
+ * chunk_bytes; 0 = chosen from n).  path: 1 = the five-step pipeline (bitmap, plan, count
+ * walk, scan, emit walk); 2 = fused (each lane finds its own cut, no bitmap; count walk,
+ * scan and emit walk as separate launches); 3 = fused in one pass (windowed scans only,
+ * else as 2): 256-lane workgroups take their lanes in order, count-walk them, find their
+ * first output slot by a look-back over the earlier workgroups' published totals, and
+ * emit, all in one launch; 0 = default: 3 where it applies, else 2.  block_threads:
+ * threads per walk workgroup, 256, 512 or 1024 (0 = the largest whose LDS fits; one pass
+ * uses 256 and a default path given another value takes path 2).  emit: 0 = default,
+ * 1 = lane emit only.  By default a scan whose automaton is monotone (no live edge from an
+ * accepting to a non-accepting state), counts every token end in its mode (exact mode, or
+ * no discarded kind) and has at most 256 rows uses the windowed emit: the count walk
+ * records checkpoints every 64 bytes and the emit walk runs one thread per 64-byte
+ * sub-slice; a scan with a halted slice or a slice of 2^24 bytes or more falls back to the
+ * lane emit (one thread per slice) on the device.  All write the same outputs.  events:
+ * optional array of LEX_NPHASES + 1 hipEvent_t (passed as void*, created by the caller)
+ * recorded on the scan's stream at the phase boundaries: [0] start, [1] after planning
+ * (steps a, b), [2] after the count walk (c), [3] after the scan (d), [4] after the emit
+ * walk (e).  In one pass, [1] follows the reset of the look-back state, [2] the one-pass
+ * launch (planning, count walk and windowed emit) and [4] the lane emit's fallback. */
 enum { LEX_NPHASES = 4 };
 enum { LEX_EMIT_DEFAULT = 0, LEX_EMIT_LANE = 1 };
 typedef struct {
@@ -146,6 +152,18 @@ typedef struct {
   int32_t emit;
   void *const *events;
 } lex_run_opts;
+
+/* The configuration lex_run would use for n bytes in this mode under opts (NULL =
+ * defaults): for tools and benchmarks that attribute time and bytes to kernels.  path is
+ * 1, 2 or 3 as in lex_run_opts (never 0); windowed: the windowed emit applies.  Returns
+ * what lex_run would return for these arguments (LEX_EINVAL, LEX_ELIMIT) or LEX_OK. */
+typedef struct {
+  uint32_t lane_bytes;
+  uint32_t block_threads;
+  int32_t path;
+  int32_t windowed;
+} lex_plan_info;
+int lex_plan(const lex_dfa *dfa, uint64_t n, int mode, const lex_run_opts *opts, lex_plan_info *out);
 
 /* Device workspace bytes lex_run needs for n input bytes under opts (NULL = defaults). */
 size_t lex_workspace_size(const lex_dfa *dfa, uint64_t n, int mode, const lex_run_opts *opts);

@@ -38,6 +38,11 @@ LEX_NPHASES = 4
 LEX_EMIT_DEFAULT, LEX_EMIT_LANE = 0, 1
 
 
+class PlanInfo(C.Structure):
+    _fields_ = [("lane_bytes", C.c_uint32), ("block_threads", C.c_uint32), ("path", C.c_int32),
+                ("windowed", C.c_int32)]
+
+
 class RunOpts(C.Structure):
     _fields_ = [("chunk_bytes", C.c_uint64), ("lane_bytes", C.c_uint32), ("path", C.c_int32),
                 ("block_threads", C.c_int32), ("emit", C.c_int32), ("events", C.c_void_p)]
@@ -68,6 +73,7 @@ def lib():
         "lex_info": (C.c_int, [P, C.POINTER(Info)]),
         "lex_tables": (C.c_int, [P, C.c_int, P, SZ, P, P, SZ]),
         "lex_workspace_size": (SZ, [P, U64, C.c_int, P]),
+        "lex_plan": (C.c_int, [P, U64, C.c_int, P, P]),
         "lex_run": (C.c_int, [P, P, U64, C.c_int, P, P, P, U64, P, P, SZ, P, P]),
         "lex_cert_bitmap": (C.c_int, [P, P, U64, C.c_int, P, P]),
         "lex_batch_create": (C.c_int, [P, P, U32, P, C.c_char_p, SZ]),
@@ -91,6 +97,6 @@ def check(rc: int, msg: str = ""):
 
 def exported_symbols():
     return sorted(n for n in ("lex_compile", "lex_compile_table", "lex_free", "lex_cert", "lex_info",
-                              "lex_tables", "lex_workspace_size", "lex_run", "lex_cert_bitmap",
+                              "lex_tables", "lex_workspace_size", "lex_plan", "lex_run", "lex_cert_bitmap",
                               "lex_batch_create", "lex_batch_free", "lex_batch_workspace_size",
                               "lex_run_batch"))

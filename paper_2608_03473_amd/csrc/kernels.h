@@ -56,6 +56,10 @@ struct Plan {
   uint32_t kslots;
   int32_t *lnz;            // nlanes: last non-empty lane at or before it in its workgroup, or -1
   int32_t *blk_lnz;        // nblocks: last non-empty lane of the earlier workgroups, or -1
+  // One pass (windowed scans, 256-lane workgroups): per workgroup of lanes, the status word
+  // of the decoupled look-back, and the counter that hands the workgroups out in order.
+  uint64_t *chunk_st;      // nblocks
+  uint32_t *chunk_ctr;
 };
 
 constexpr uint32_t kWin = 64;  // window of the windowed emit
@@ -69,6 +73,10 @@ size_t workspace_bytes(uint32_t n, uint32_t lane_bytes, uint32_t block, int pipe
 size_t walk_lds_bytes(int nrows, uint32_t block, bool emit);
 // Dynamic LDS of a windowed-emit workgroup (the table and four wave stages).
 size_t window_lds_bytes(int nrows);
+// Dynamic LDS of a one-pass workgroup (256 lanes: the table, the lanes' slices and
+// prefixes, and four wave stages).
+size_t onepass_lds_bytes(int nrows);
+constexpr uint32_t kChunkLanes = 256;  // lanes per one-pass workgroup
 bool carve(void *ws, size_t ws_bytes, uint32_t n, uint32_t lane_bytes, uint32_t block, int pipeline,
            int windowed, Plan &p);
 
@@ -94,6 +102,12 @@ hipError_t run_pipeline(const DevTable &t, const CertMap &cm, const uint8_t *in,
 hipError_t run_fused(const DevTable &t, const CertMap &cm, const uint8_t *cert_lut, const uint8_t *in,
                      const Plan &p, bool serial, uint8_t *kinds, uint32_t *lens, uint64_t *offs, uint64_t cap,
                      ResultDev *res, hipStream_t s, hipEvent_t const *ev);
+
+// One pass (windowed scans, block == kChunkLanes): plan, count walk, look-back and windowed
+// emit in one launch, then the scan and the lane emit's fallback.
+hipError_t run_onepass(const DevTable &t, const CertMap &cm, const uint8_t *cert_lut, const uint8_t *in,
+                       const Plan &p, bool serial, uint8_t *kinds, uint32_t *lens, uint64_t *offs, uint64_t cap,
+                       ResultDev *res, hipStream_t s, hipEvent_t const *ev);
 
 // Batched documents.  The instances' tables are rebased into one combined table (rows of
 // instance k follow those of instances 0..k-1); start/sink/fail are row byte offsets in it.

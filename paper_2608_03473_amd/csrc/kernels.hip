@@ -13,7 +13,8 @@
 //                    slice.
 //   (c) k_count      every lane runs the longest-match loop of Section 3 on its slice
 //                    [cut_j, cut_j+1) from the start row, treating the slice end as the end
-//                    of the input; the packed transition table lives in LDS.
+//                    of the input; the packed transition table lives in LDS.  The fused
+//                    path places each lane's cut inside this kernel (lane_slice).
 //   (d) k_scan       exclusive prefix of the per-lane counts; the first lane whose walk
 //                    halted fixes the output length and, by Corollary 1, truncates it.
 //   (e) k_emit       every lane up to the first halted one walks again and writes its
@@ -22,6 +23,13 @@
 //                    Tokens are staged in a 64-byte per-lane LDS ring and leave in whole,
 //                    aligned 32-byte sectors (8 lengths or 32 kinds at a time), so the
 //                    emit walk issues few, full-width memory requests.
+//       k_emit_win   the windowed emit (monotone automata whose token ends are all
+//                    counted): one thread per 64-byte window, restarted from the count
+//                    walk's checkpoint, tokens staged per wave and written out coalesced.
+//   k_onepass        (b)-(e) for windowed scans in one launch: 256-lane groups taken in
+//                    order plan, count, find their first output slot by a decoupled
+//                    look-back over the earlier groups' totals, and emit their windows.
+//   Batches of documents (lex_run_batch) have kernels of their own, further below.
 //
 // Table entries (layout in compile.h): COUNT (bit 0), EMIT (bit 1), the next row's
 // swizzle (bits 2..6), ACC (bit 7), the next row's byte offset in bits 10..23 and the
@@ -452,6 +460,28 @@ __device__ __forceinline__ uint32_t byte_of(const uint4 &v, int k) {
   return (w >> (8 * (k & 3))) & 0xFFu;
 }
 
+// The 128-byte memory line at position P of in[0, n) (in + P is 128-aligned; bytes
+// outside [0, n) read as 0).
+__device__ __forceinline__ void load_line(const uint8_t *in, int64_t P, uint32_t n, uint4 (&v)[8]) {
+  if (P >= 0 && P + 128 <= (int64_t)n) {
+    const uint4 *src = reinterpret_cast<const uint4 *>(in + P);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = src[i];
+  } else {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = load_block(in, P + 16 * i, n);
+  }
+}
+
+// Bits [lo, hi) of the 32-bit word that covers bits [32 w, 32 w + 32) of a longer mask.
+__device__ __forceinline__ uint32_t range_word(int64_t lo, int64_t hi, int w) {
+  const int64_t a = min<int64_t>(32, max<int64_t>(0, lo - 32 * w));
+  const int64_t b = min<int64_t>(32, max<int64_t>(0, hi - 32 * w));
+  const uint32_t below_b = b >= 32 ? ~0u : (1u << (uint32_t)b) - 1u;
+  const uint32_t below_a = a >= 32 ? ~0u : (1u << (uint32_t)a) - 1u;
+  return below_b & ~below_a;
+}
+
 // Checkpoints of the count walk for the windowed emit.  Windows are the kWin-aligned
 // stretches of the input's address space: window i starts at position i * kWin - mis0
 // (mis0 = the input's address modulo kWin).  When a lane's walk reaches a window start
@@ -602,6 +632,105 @@ __device__ __forceinline__ bool walk(LaneState &L, Ring &r, const Tables &tb, co
   return finish<EMIT, MONO>(L, r, tb, in, e);
 }
 
+__device__ __forceinline__ uint32_t wave_max(uint32_t v) {
+#pragma unroll
+  for (int d = 32; d; d >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, d));
+  return v;
+}
+
+// Certified bytes of a 16-byte block as a 16-bit mask (bit k = byte k).
+__device__ __forceinline__ uint32_t match16(const uint4 &v, const CertArg &ca, const uint8_t *lut) {
+  const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+  uint32_t m = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    uint32_t x = 0;
+    if (ca.np >= 0) {
+      uint32_t z = 0;
+#pragma unroll
+      for (int i = 0; i < 8; ++i)  // fixed trip count: the patterns stay in registers
+        if (i < ca.np) z |= zero_bytes(w[q] ^ ca.pat[i]);
+      x = gather4(z);
+    } else {
+      x = match_word_lut(w[q], lut);
+    }
+    m |= x << (4 * q);
+  }
+  return m;
+}
+
+// Count walk of a monotone automaton over the slice [s, e) in whole 128-byte memory lines,
+// the lanes of a wave stepping through their lines together (same result as
+// walk<false, true, false>; a per-lane head, body and tail would leave most lanes idle while
+// the others finish theirs).  A line inside the slice of every lane still walking takes the
+// plain path; otherwise every lane takes the masked path, where the row is held at the start
+// before s, frozen from e on, and count bits outside [s, e) are dropped.  Lanes past their
+// last line walk along and keep nothing.  CK records the checkpoints of walk<..., CK>: the
+// window starts of each line that lie strictly inside the slice.  Every lane of the wave
+// must call this in the same control flow; `live` is false for lanes without a slice.
+// Returns true if the slice halted.
+template <bool CK>
+__device__ __forceinline__ bool walk_lines(LaneState &L, Ring &r, const Tables &tb, const uint8_t *in, uint32_t n,
+                                           uint32_t s, uint32_t e, bool live, const CkSink &ck) {
+  L.st = tb.start;
+  L.tok = s;
+  L.lacc = s;
+  L.lrow = tb.start;
+  L.cnt = 0;
+  live = live && s < e;
+  const int64_t mis = (int64_t)(reinterpret_cast<uintptr_t>(in) & 127);
+  const int64_t P0 = (((int64_t)s + mis) & ~int64_t(127)) - mis;  // the line holding s
+  const uint32_t nl = live ? (uint32_t)(((int64_t)e - P0 + 127) >> 7) : 0;
+  const uint32_t maxl = wave_max(nl);
+  for (uint32_t li = 0; li < maxl; ++li) {
+    const int64_t P = P0 + 128 * (int64_t)li;
+    const bool mine = li < nl;
+    const bool full = !mine || (P >= (int64_t)s && P + 128 <= (int64_t)e);
+    uint4 v[8];  // a lane past its last line reloads that line (any defined bytes do)
+    load_line(in, mine ? P : P0 + 128 * (int64_t)(nl ? nl - 1 : 0), n, v);
+    const uint32_t st0 = L.st, cnt0 = L.cnt, tok0 = L.tok;
+    const uint32_t blk = (uint32_t)P;  // positions blk + q modulo 2^32
+    if (__all(full)) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        if (CK && i % 4 == 0 && ck.main && mine && P + 16 * i > (int64_t)s) ck_record(ck, L, blk + 16 * i);
+        block16<false, true, false>(L, r, tb, v[i], blk + 16 * i);
+      }
+    } else {
+      // steps q < lo are before s, q >= hi at or after e (clamped: q and 16 i lie in [0, 128))
+      const int lo = (int)max<int64_t>(-1, min<int64_t>(128, (int64_t)s - P));
+      const int hi = (int)max<int64_t>(0, min<int64_t>(129, (int64_t)e - P));
+      uint32_t st = L.st;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        if (CK && i % 4 == 0 && ck.main && mine && 16 * i > lo && 16 * i < hi) {
+          L.st = st & kRowMask;
+          ck_record(ck, L, blk + 16 * i);
+        }
+        uint32_t m = 0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+          const int q = 16 * i + k;
+          const uint32_t y = entry_from(tb, st, byte_of(v[i], k));
+          st = q < lo ? tb.start : q < hi ? y : st;
+          m = __builtin_amdgcn_alignbit(y, m, 1);
+        }
+        m &= range_word(lo - 16 * i + 16, hi - 16 * i + 16, 0) & 0xFFFF0000u;  // bit 16 + k: step 16 i + k
+        L.cnt += __builtin_popcount(m);
+        L.tok = m ? blk + 16 * i + 15 - __clz(m) : L.tok;
+      }
+      L.st = st & kRowMask;
+    }
+    if (!mine) {
+      L.st = st0;
+      L.cnt = cnt0;
+      L.tok = tok0;
+    }
+  }
+  if (!live) return false;
+  return finish<false, true>(L, r, tb, in, e);
+}
+
 struct WalkArgs {
   const uint32_t *table;  // global copies, staged into LDS
   const uint8_t *rowinfo;
@@ -631,6 +760,8 @@ struct WalkArgs {
   uint32_t block_shift;   // log2(block)
   FastDiv lane_div;       // division by lane_bytes
   int fallback_only;      // lane emit: run only when the windowed emit cannot
+  uint64_t *chunk_st;     // one pass: look-back status per workgroup of lanes
+  uint32_t *chunk_ctr;    // one pass: next workgroup of lanes to take
   // emit
   const uint32_t *meta;
   ResultDev *res;
@@ -688,28 +819,9 @@ __device__ __forceinline__ void stage_tables(const WalkArgs &a, const Lds &l, bo
   __syncthreads();
 }
 
-// Certified bytes of a 16-byte block as a 16-bit mask (bit k = byte k).
-__device__ __forceinline__ uint32_t match16(const uint4 &v, const CertArg &ca, const uint8_t *lut) {
-  const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-  uint32_t m = 0;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    uint32_t x = 0;
-    if (ca.np >= 0) {
-      uint32_t z = 0;
-      for (int i = 0; i < ca.np; ++i) z |= zero_bytes(w[q] ^ ca.pat[i]);
-      x = gather4(z);
-    } else {
-      x = match_word_lut(w[q], lut);
-    }
-    m |= x << (4 * q);
-  }
-  return m;
-}
-
 // Fused planning: the first certified byte in [x, x + span) (or `none`), 16 bytes at a
 // time.
-__device__ uint32_t search_cert(const uint8_t *in, uint32_t n, const CertArg &ca, const uint8_t *lut, uint32_t x,
+__device__ __forceinline__ uint32_t search_cert(const uint8_t *in, uint32_t n, const CertArg &ca, const uint8_t *lut, uint32_t x,
                                 uint32_t span, uint32_t none) {
   const uint32_t end = (uint32_t)min<uint64_t>((uint64_t)x + span, n);
   int64_t blk = (int64_t)x - (int64_t)(reinterpret_cast<uintptr_t>(in + x) & 15);
@@ -760,42 +872,50 @@ __device__ __forceinline__ void lane_slice(const WalkArgs &a, uint32_t j, const 
   e = next != kNone ? next : search_cert(a.in, a.n, a.ca, lut, (uint32_t)x1, a.n - (uint32_t)x1, a.n);
 }
 
+__device__ __forceinline__ CkSink ck_sink(const WalkArgs &a, uint32_t j) {
+  CkSink ck{};
+  ck.base = reinterpret_cast<uintptr_t>(a.in);
+  ck.main = a.ck;
+  ck.over = a.ck_over;
+  ck.nlanes = a.nlanes;
+  ck.kslots = a.kslots;
+  ck.j = j;
+  ck.jl = j * a.lane_bytes;
+  ck.mis0 = (uint32_t)(ck.base & (kWin - 1));
+  return ck;
+}
+
 // CK: record checkpoints for the windowed emit (monotone automata only).
 template <bool MONO, bool FUSED, bool CK>
-__global__ void __launch_bounds__(1024) k_count(WalkArgs a) {
+__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) k_count(WalkArgs a) {
   const Lds l = carve_lds(a.nrows);
   stage_tables(a, l, FUSED);
   const Tables tb{lds_bytes_of(l.T), l.info, l.kind, a.sink, a.fail, 0};
   const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
   uint32_t cnt = 0, fail = kNone, nonempty = 0, big = 0;
   uint32_t s = 0, e = 0;
+  const bool active = j < a.nlanes;
   lane_slice<FUSED>(a, j, l.lut, l.xchg, s, e);
-  if (j < a.nlanes) {
-    if (FUSED) {
-      a.cuts[j] = s;
-      a.ends[j] = e;
-    }
-    LaneState L;
-    L.cnt = 0;
-    Ring r{};
-    bool halted;
-    if (CK) {
-      // checkpoints hold the count in 24 bits: longer slices record none, and the
-      // windowed emit then stands down for the whole scan
-      big = e - s >= (1u << 24);
-      CkSink ck{};
-      ck.base = reinterpret_cast<uintptr_t>(a.in);
-      ck.main = big ? nullptr : a.ck;
-      ck.over = a.ck_over;
-      ck.nlanes = a.nlanes;
-      ck.kslots = a.kslots;
-      ck.j = j;
-      ck.jl = j * a.lane_bytes;
-      ck.mis0 = (uint32_t)(ck.base & (kWin - 1));
-      halted = walk<false, MONO, false, true>(L, r, tb, a.in, a.n, s, e, ck);
-    } else {
-      halted = walk<false, MONO, false>(L, r, tb, a.in, a.n, s, e);
-    }
+  LaneState L;
+  L.cnt = 0;
+  Ring r{};
+  bool halted = false;
+  if (MONO) {
+    // every lane of the wave walks its lines together (walk_lines holds wave votes)
+    CkSink ck{};
+    if (CK) ck = ck_sink(a, j);
+    halted = walk_lines<CK>(L, r, tb, a.in, a.n, s, e, active, ck);
+    // checkpoints hold the count in 24 bits: after a longer slice the windowed emit
+    // stands down for the whole scan
+    if (CK) big = active && e - s >= (1u << 24);
+  } else if (active) {
+    halted = walk<false, false, false>(L, r, tb, a.in, a.n, s, e);
+  }
+  if (active && FUSED) {
+    a.cuts[j] = s;
+    a.ends[j] = e;
+  }
+  if (active) {
     cnt = L.cnt;
     a.counts[j] = cnt;
     if (halted) fail = j;
@@ -1113,6 +1233,105 @@ __device__ __forceinline__ void win_walk(const Tables &tb, const WalkArgs &a, co
   }
 }
 
+// One tile of 64 windows, window i on this lane (valid: i is one of the tile's windows;
+// edge: some of its positions may lie outside [0, n)).  o_first: the tile's first output
+// slot; o_end: one past its last output when `exact`, else a bound on it (the walk then
+// counts the outputs); out_end: bound on this window's outputs (the next window's first
+// slot when known); next_fresh: a lane starts at the next window's first byte; P: start of
+// the token in progress at the tile's start; span_end: end of the tile's bytes; lim: no
+// output at or above it.  Staged when the range fits the stage (see the kernel notes),
+// else each token goes straight to global memory.
+__device__ __forceinline__ void win_tile(const Tables &tb, const WalkArgs &a, uint32_t *stage, uint32_t lane,
+                                         const WinMeta &cur, uint32_t i, bool valid, bool edge, const Win64 &dat,
+                                         int64_t wp, uint32_t nwin, uint32_t o_first, uint32_t o_end, bool exact,
+                                         uint32_t out_end, uint32_t next_fresh, uint32_t P, uint32_t span_end,
+                                         uint32_t lim) {
+  const uint32_t stage_addr = (uint32_t)(size_t)(lds_u32 *)stage;
+  // slot q holds output o_first - pad + q; pad >= 4 leaves slot pad - 1 free to hold end
+  // 0, the start of the tile's first token (so every length is a difference of ends)
+  const uint32_t pad = (o_first & 3) + 4;
+  const bool staged = o_first <= o_end && o_end <= lim && o_end - o_first + pad + 3 <= kStageWords - 64 &&
+                      span_end - P < (1u << 24);
+  uint32_t st = cur.st;
+  WinOut w;
+  uint32_t d0 = 0;
+  if (staged) {
+    // spill words: the stage's first 64; slots follow, so 0 < D < 4 * kStageWords
+    w.G = stage_addr + 4 * lane;
+    w.D = d0 = 4 * (64 - lane + pad + (cur.out - o_first));
+    w.base = P;
+    if (lane == 0) stage[64 + pad - 1] = 0;
+    if (valid) {
+      if (edge) win_walk<true, true>(tb, a, dat, wp, a.n, st, w);
+      else win_walk<true, false>(tb, a, dat, wp, a.n, st, w);
+    }
+  } else {
+    w.tok = cur.tok;
+    w.o = cur.out;
+    w.lim = valid ? min(out_end, lim) : cur.out;
+    if (valid) {
+      if (edge) win_walk<false, true>(tb, a, dat, wp, a.n, st, w);
+      else win_walk<false, false>(tb, a, dat, wp, a.n, st, w);
+    }
+  }
+  // The input's end, or a lane starting at the next window's first byte: the token in
+  // progress ends here, as the lane walk's slice end made it (the next window starts
+  // afresh and does not see it).
+  st &= kRowMask;
+  if (valid && (i + 1 == nwin || next_fresh) && st != 0) {
+    const uint32_t end = i + 1 == nwin ? a.n : (i + 1) * kWin - (uint32_t)(reinterpret_cast<uintptr_t>(a.in) & (kWin - 1));
+    const uint32_t row = st >> kRowShift;
+    if ((tb.info[row] & kInfoAcc) && (tb.info[row] & kInfoCount)) {
+      if (staged) {
+        *(lds_u32 *)(size_t)(w.G + w.D) = (uint32_t)tb.kind[row] | ((end - P) << 8);
+        w.D += 4;
+      } else if (w.o < w.lim) {
+        a.kinds[w.o] = tb.kind[row];
+        a.lens[w.o] = end - w.tok;
+        if (a.offs) a.offs[w.o] = w.tok;
+      }
+    }
+  }
+  if (!staged) return;  // wave-uniform
+  // the range's length: known, or counted by the walk (the last valid window's end slot)
+  const uint32_t total = exact ? o_end - o_first
+                               : wave_max(valid ? cur.out - o_first + (w.D - d0) / 4 : 0);
+  wave_sync();
+  // write the range out, four slots per lane and step: lengths are differences of
+  // consecutive ends (slot pad - 1 holds 0), kinds the low bytes
+  const uint32_t o0 = o_first - pad;
+  const uint32_t *slots = stage + 64;
+  for (uint32_t q = 4 + lane * 4; q < pad + total; q += 256) {
+    const uint4 v = *reinterpret_cast<const uint4 *>(slots + q);
+    const uint32_t e0 = slots[q - 1] >> 8, e1 = v.x >> 8, e2 = v.y >> 8, e3 = v.z >> 8, e4 = v.w >> 8;
+    const uint4 len = make_uint4(e1 - e0, e2 - e1, e3 - e2, e4 - e3);
+    const uint32_t kd = __builtin_amdgcn_perm(__builtin_amdgcn_perm(v.w, v.z, 0x0C0C0400u),
+                                              __builtin_amdgcn_perm(v.y, v.x, 0x0C0C0400u), 0x05040100u);
+    const uint32_t o = o0 + q;
+    if (q >= pad && q + 4 <= pad + total) {
+      *reinterpret_cast<uint4 *>(a.lens + o) = len;
+      *reinterpret_cast<uint32_t *>(a.kinds + o) = kd;
+      if (a.offs) {
+        a.offs[o] = P + e0;
+        a.offs[o + 1] = P + e1;
+        a.offs[o + 2] = P + e2;
+        a.offs[o + 3] = P + e3;
+      }
+    } else {
+      const uint32_t lv[4] = {len.x, len.y, len.z, len.w}, sv[4] = {e0, e1, e2, e3};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (q + k >= pad && q + k < pad + total) {
+          a.lens[o + k] = lv[k];
+          a.kinds[o + k] = (uint8_t)(kd >> (8 * k));
+          if (a.offs) a.offs[o + k] = P + sv[k];
+        }
+      }
+    }
+  }
+  wave_sync();
+}
+
 // A tile is 64 windows; each wave walks a contiguous run of tiles.  Software pipeline:
 // the next tile's bytes and the state of the tile after it load while a tile walks.
 template <bool FUSED>
@@ -1123,7 +1342,6 @@ __global__ void __launch_bounds__(256) k_emit_win(WalkArgs a) {
   const Tables tb{lds_bytes_of(l.T), l.info, l.kind, a.sink, a.fail, 0};
   const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   uint32_t *stage = reinterpret_cast<uint32_t *>(l.ring) + wid * kStageWords;
-  const uint32_t stage_addr = (uint32_t)(size_t)(lds_u32 *)stage;
   const uintptr_t base = reinterpret_cast<uintptr_t>(a.in);
   const uint32_t mis0 = (uint32_t)(base & (kWin - 1));
   const uint32_t nwin = (uint32_t)(((uint64_t)a.n + mis0 + kWin - 1) / kWin);
@@ -1141,111 +1359,283 @@ __global__ void __launch_bounds__(256) k_emit_win(WalkArgs a) {
   Win64 dat = is_edge(t_lo) ? win_load<true>(a.in, wpos(t_lo), a.n) : win_load<false>(a.in, wpos(t_lo), a.n);
   for (uint32_t tile = t_lo; tile < t_hi; ++tile) {
     const uint32_t i = tile * 64 + lane;
-    const bool valid = i < nwin;
-    const bool edge = is_edge(tile);
     Win64 ndat = dat;
     if (tile + 1 < t_hi)
       ndat = is_edge(tile + 1) ? win_load<true>(a.in, wpos(tile + 1), a.n) : win_load<false>(a.in, wpos(tile + 1), a.n);
+    // the state of the tile after next, and the first-round loads of the one after that:
+    // issued here, they complete while this tile walks
+    const WinMeta n2 = win_meta(a, r1, (tile + 2) * 64 + lane, nwin, ntok);
+    r1 = win_r1<FUSED>(a, (tile + 3) * 64 + lane, mis0, nwin);
     // this window's range of output slots ends where the next window's begins
     // (every shuffle runs with the whole wave active: a lane reading from an inactive
     // lane gets no defined value)
     const uint32_t o_first = __shfl(cur.out, 0), o_next = __shfl(nxt.out, 0);
     const uint32_t down = __shfl_down(cur.out, 1), fdown = __shfl_down(cur.fresh, 1);
     const uint32_t f_next = __shfl(nxt.fresh, 0);
-    const uint32_t out_end = lane < 63 ? down : o_next;
-    const uint32_t next_fresh = lane < 63 ? fdown : f_next;
     const uint32_t P = __shfl(cur.tok, 0);  // start of the token in progress at the tile's start
-    const uint32_t total = o_next - o_first;
-    const uint32_t pad = o_first & 3;
-    const int64_t wp = wpos(tile);
     const uint32_t span_end = (uint32_t)min<int64_t>((int64_t)(tile + 1) * 64 * kWin - mis0, a.n);
-    const bool staged = o_first <= o_next && o_next <= ntok && total + pad + 3 <= kStageWords - 64 &&
-                        span_end - P < (1u << 24);
-    uint32_t st = cur.st;
-    WinOut w;
-    if (staged) {
-      // spill words: the stage's first 64; slots follow, so 0 < D < 4 * kStageWords
-      w.G = stage_addr + 4 * lane;
-      w.D = 4 * (64 - lane + pad + (cur.out - o_first));
-      w.base = P;
-      if (valid) {
-        if (edge) win_walk<true, true>(tb, a, dat, wp, a.n, st, w);
-        else win_walk<true, false>(tb, a, dat, wp, a.n, st, w);
-      }
-    } else {
-      w.tok = cur.tok;
-      w.o = cur.out;
-      w.lim = valid ? min(out_end, ntok) : cur.out;
-      if (valid) {
-        if (edge) win_walk<false, true>(tb, a, dat, wp, a.n, st, w);
-        else win_walk<false, false>(tb, a, dat, wp, a.n, st, w);
-      }
-    }
-    // The input's end, or a lane starting at the next window's first byte: the token in
-    // progress ends here, as the lane walk's slice end made it (the next window starts
-    // afresh and does not see it).
-    st &= kRowMask;
-    if (valid && (i + 1 == nwin || next_fresh) && st != 0) {
-      const uint32_t end = i + 1 == nwin ? a.n : (i + 1) * kWin - mis0;
-      const uint32_t row = st >> kRowShift;
-      if ((tb.info[row] & kInfoAcc) && (tb.info[row] & kInfoCount)) {
-        if (staged) {
-          *(lds_u32 *)(size_t)(w.G + w.D) = (uint32_t)tb.kind[row] | ((end - P) << 8);
-        } else if (w.o < w.lim) {
-          a.kinds[w.o] = tb.kind[row];
-          a.lens[w.o] = end - w.tok;
-          if (a.offs) a.offs[w.o] = w.tok;
-        }
-      }
-    }
-    // the state of the tile after next, before this tile's stores
-    const WinMeta n2 = win_meta(a, r1, (tile + 2) * 64 + lane, nwin, ntok);
-    r1 = win_r1<FUSED>(a, (tile + 3) * 64 + lane, mis0, nwin);
-    if (staged) {
-      wave_sync();
-      // write the range out: slot q holds output o_first - pad + q
-      const uint32_t o0 = o_first - pad;
-      const uint32_t *slots = stage + 64;
-      for (uint32_t q = lane * 4; q < pad + total; q += 256) {
-        const uint4 v = *reinterpret_cast<const uint4 *>(slots + q);
-        const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
-        uint32_t prev = q > pad ? slots[q - 1] >> 8 : 0;
-        uint32_t len[4], kd = 0, sp[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const uint32_t endp = wv[k] >> 8;
-          const uint32_t pv = q + k > pad ? prev : 0;
-          len[k] = endp - pv;
-          sp[k] = P + pv;
-          kd |= (wv[k] & 0xFFu) << (8 * k);
-          prev = endp;
-        }
-        if (q >= pad && q + 4 <= pad + total) {
-          *reinterpret_cast<uint4 *>(a.lens + o0 + q) = make_uint4(len[0], len[1], len[2], len[3]);
-          *reinterpret_cast<uint32_t *>(a.kinds + o0 + q) = kd;
-          if (a.offs) {
-#pragma unroll
-            for (int k = 0; k < 4; ++k) a.offs[o0 + q + k] = sp[k];
-          }
-        } else {
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            if (q + k >= pad && q + k < pad + total) {
-              a.lens[o0 + q + k] = len[k];
-              a.kinds[o0 + q + k] = (uint8_t)(kd >> (8 * k));
-              if (a.offs) a.offs[o0 + q + k] = sp[k];
-            }
-          }
-        }
-      }
-      wave_sync();
-    }
+    win_tile(tb, a, stage, lane, cur, i, i < nwin, is_edge(tile), dat, wpos(tile), nwin, o_first, o_next, true,
+             lane < 63 ? down : o_next, lane < 63 ? fdown : f_next, P, span_end, ntok);
     cur = nxt;
     nxt = n2;
     dat = ndat;
   }
 }
 
+// ------------------------------------------------- (b)-(e) in one pass over lane groups
+// Windowed scans in one launch.  Each workgroup takes groups of 256 consecutive lanes in
+// order from a counter and, for each group: plans and count-walks its lanes (as k_count,
+// recording checkpoints); publishes the group's token total; finds the group's first output
+// slot by a decoupled look-back over the earlier groups' published totals and prefixes
+// (the counter hands groups out in order, so every earlier group is already running); then
+// emits the windows whose first byte lies in its own lanes' slices [S, E) exactly as the
+// windowed emit does.  The group's bytes are read a second time while still in the caches,
+// and groups in different phases overlap the count walk's table lookups with the emit's
+// stores.  Owners, prefixes and checkpoints all come from the group itself: the one thing a
+// group needs about later ones is whether a lane starts at the first window after E, which
+// it decides from the bytes there (a lane starts at y exactly when y is the first certified
+// byte at or after the lane's target and lies before the next target).
+//
+// Each group also writes what k_count writes (slices, counts, prefixes, block totals and
+// flags), so k_scan and the lane emit's fallback run after it unchanged: a halted slice, a
+// slice too long for the checkpoints, or a look-back that did not finish (bounded spin)
+// leaves the emit to them, and a group emits only when no earlier group halted.
+constexpr uint64_t kStAgg = 1ull << 62, kStIncl = 2ull << 62, kStPoison = 1ull << 61;
+constexpr uint64_t kStValue = (1ull << 61) - 1;
+constexpr uint32_t kSpinLimit = 1u << 22;
+
+__host__ __device__ inline size_t one_lds_bytes(int nrows) {
+  return lds_ring_offset(nrows) + (size_t)kChunkLanes * 13 + 16 + (size_t)kWinWaves * kStageWords * 4;
+}
+
+// First window whose first byte is at or after position x (window 0 starts at 0, window
+// i >= 1 at i * kWin - mis0).
+__device__ __forceinline__ uint32_t win_from(uint32_t x, uint32_t mis0) {
+  return x ? (uint32_t)(((uint64_t)x + mis0 + kWin - 1) / kWin) : 0;
+}
+
+struct GroupLds {
+  const uint32_t *s, *e, *pre;  // per lane of the group: slice, exclusive prefix of counts
+  const uint8_t *lnz;           // last non-empty lane at or before it (0xFF: none)
+};
+
+// Window i of a group's range [i_lo, i_hi): owner, state, token start and output slot.
+// Past the range: out = bound, fresh = whether a lane starts at window i_hi.
+__device__ __forceinline__ WinMeta group_meta(const WalkArgs &a, const GroupLds &g, uint32_t i, uint32_t i_hi,
+                                              uint32_t c0, uint32_t last, uint32_t Pc, uint32_t mis0,
+                                              uint32_t fresh_after, uint32_t bound) {
+  WinMeta m{0, 0, bound, fresh_after};
+  if (i >= i_hi) return m;
+  const uint32_t W = i ? i * kWin - mis0 : 0;
+  const uint32_t j0 = fdiv(W, a.lane_div);
+  uint32_t o = last;  // a window past the group's nominal range lies in its last slice
+  bool here = false;
+  if (j0 < c0 + kChunkLanes) {
+    const uint32_t q = j0 - c0;  // W >= S >= c0 * lane_bytes, so j0 >= c0
+    here = g.s[q] < g.e[q] && g.s[q] <= W;
+    o = here ? q : (q && g.lnz[q - 1] != 0xFF ? g.lnz[q - 1] : last);
+  }
+  const uint32_t base = Pc + g.pre[o];
+  if (here && g.s[o] == W) {  // the owner starts here: a fresh token
+    m.st = 0;
+    m.tok = W;
+    m.out = base;
+    m.fresh = 1;
+    return m;
+  }
+  const uint32_t j = c0 + o;
+  const uint32_t k = (W - j * a.lane_bytes) / kWin;
+  const uint2 c = k < a.kslots ? a.ck[(size_t)k * a.nlanes + j] : a.ck_over[i];
+  m.st = row_state(c.x >> 24);
+  m.tok = c.y;
+  m.out = base + (c.x & 0xFFFFFFu);
+  m.fresh = 0;
+  return m;
+}
+
+__global__ void __launch_bounds__(256) k_onepass(WalkArgs a) {
+  const Lds l = carve_lds(a.nrows);
+  stage_tables(a, l, true);
+  const Tables tb{lds_bytes_of(l.T), l.info, l.kind, a.sink, a.fail, 0};
+  uint32_t *ls = reinterpret_cast<uint32_t *>(l.ring), *le = ls + kChunkLanes, *lpre = le + kChunkLanes;
+  uint8_t *llnz = reinterpret_cast<uint8_t *>(lpre + kChunkLanes);
+  uint32_t *bc = reinterpret_cast<uint32_t *>(llnz + kChunkLanes);  // group index, prefix, emit flag, fresh
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  uint32_t *stage = bc + 4 + wid * kStageWords;
+  const uint32_t mis0 = (uint32_t)(reinterpret_cast<uintptr_t>(a.in) & (kWin - 1));
+  const uint32_t nwin = (uint32_t)(((uint64_t)a.n + mis0 + kWin - 1) / kWin);
+  const uint32_t ngroups = (a.nlanes + kChunkLanes - 1) / kChunkLanes;
+  const uint32_t cap = (uint32_t)min<uint64_t>(a.cap, 0xFFFFFFFFu);
+  const GroupLds g{ls, le, lpre, llnz};
+  for (;;) {
+    if (tid == 0) bc[0] = atomicAdd(a.chunk_ctr, 1u);
+    __syncthreads();
+    const uint32_t c = bc[0];
+    if (c >= ngroups) break;  // the same for the whole workgroup
+    const uint32_t c0 = c * kChunkLanes, j = c0 + tid;
+    const bool active = j < a.nlanes;
+    // ---- plan and count (as k_count); the slice exchange borrows le
+    uint32_t s = 0, e = 0;
+    lane_slice<true>(a, j, l.lut, le, s, e);
+    LaneState L;
+    L.cnt = 0;
+    Ring r{};
+    const bool halted = walk_lines<true>(L, r, tb, a.in, a.n, s, e, active, ck_sink(a, j));
+    const uint32_t cnt = active ? L.cnt : 0;
+    const bool nonempty = active && s < e;
+    if (active) {
+      a.cuts[j] = s;
+      a.ends[j] = e;
+      a.counts[j] = cnt;
+    }
+    uint32_t incl = cnt, fail = active && halted ? j : kNone, ne = nonempty, big = active && e - s >= (1u << 24);
+    uint32_t smin = nonempty ? s : 0xFFFFFFFFu;
+    int32_t lz = nonempty ? (int32_t)tid : -1;
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t v = __shfl_up(incl, d);
+      const int32_t z = __shfl_up(lz, d);
+      if (lane >= d) {
+        incl += v;
+        lz = max(lz, z);
+      }
+    }
+    for (int d = 32; d; d >>= 1) {
+      fail = min(fail, (uint32_t)__shfl_xor((int)fail, d));
+      smin = min(smin, (uint32_t)__shfl_xor((int)smin, d));
+      ne += __shfl_xor(ne, d);
+      big |= __shfl_xor(big, d);
+    }
+    __syncthreads();  // every lane has read its neighbour's slice start from le
+    if (lane == 63) l.red64[wid] = ((uint64_t)(uint32_t)lz << 32) | incl;
+    if (lane == 0) {
+      l.red32[wid] = fail;
+      l.red32[4 + wid] = smin;
+      l.red32[16 + wid] = ne | (big << 31);
+    }
+    __syncthreads();
+    uint32_t pre = 0, T = 0, F = kNone, S = 0xFFFFFFFFu, NE = 0, BG = 0;
+    int32_t zmax = -1;
+    for (int w = 0; w < kWinWaves; ++w) {
+      if (w < (int)wid) {
+        pre += (uint32_t)l.red64[w];
+        lz = max(lz, (int32_t)(l.red64[w] >> 32));
+      }
+      T += (uint32_t)l.red64[w];
+      zmax = max(zmax, (int32_t)(l.red64[w] >> 32));
+      F = min(F, l.red32[w]);
+      S = min(S, l.red32[4 + w]);
+      NE += l.red32[16 + w] & 0x7FFFFFFFu;
+      BG |= l.red32[16 + w] >> 31;
+    }
+    const uint32_t epre = pre + incl - cnt;
+    if (active) {
+      a.lane_pre[j] = epre;
+      a.lnz[j] = lz >= 0 ? (int32_t)(c0 + lz) : -1;
+    }
+    ls[tid] = s;
+    le[tid] = e;
+    lpre[tid] = epre;
+    llnz[tid] = lz >= 0 ? (uint8_t)lz : 0xFF;
+    if (tid == 0) {
+      a.blk_sum[c] = T;
+      a.blk_fail[c] = F;
+      a.blk_nonempty[c] = NE;
+      a.blk_lnz[c] = zmax >= 0 ? (int32_t)(c0 + zmax) : -1;
+      // ---- publish the total, then look back for the prefix
+      const bool poison = F != kNone || BG;
+      __hip_atomic_store(&a.chunk_st[c], kStAgg | (poison ? kStPoison : 0) | T, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+      uint64_t prefix = 0;
+      bool any_poison = poison, ok = true;
+      for (uint32_t q = c; q-- > 0;) {
+        uint64_t w = 0;
+        for (uint32_t spins = 0;; ++spins) {
+          w = __hip_atomic_load(&a.chunk_st[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if ((w >> 62) != 0 || spins >= kSpinLimit) break;
+          __builtin_amdgcn_s_sleep(2);
+        }
+        if ((w >> 62) == 0) {  // not published in time: leave this group to the fallback
+          ok = false;
+          break;
+        }
+        prefix += w & kStValue;
+        any_poison = any_poison || (w & kStPoison);
+        if ((w >> 62) == 2) break;
+      }
+      if (ok)
+        __hip_atomic_store(&a.chunk_st[c], kStIncl | (any_poison ? kStPoison : 0) | (prefix + T), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+      a.blk_big[c] = BG | !ok;  // an unfinished look-back hands the scan to the fallback emit
+      bc[1] = (uint32_t)prefix;
+      bc[2] = ok && !any_poison && NE && prefix + T <= cap;
+      // whether a lane starts at the first window after the group's last slice
+      uint32_t fresh_after = 0;
+      const uint32_t E = NE ? le[llnz[kChunkLanes - 1]] : 0;
+      if (NE && E < a.n) {
+        const uint32_t i_hi = win_from(E, mis0);
+        const uint32_t W = i_hi * kWin - mis0;
+        if (W == E) {
+          fresh_after = 1;
+        } else if (W < a.n) {
+          const uint32_t t = fdiv(W, a.lane_div) * a.lane_bytes;  // the last target at or before W
+          if (t > E && l.lut[a.in[W]]) {
+            fresh_after = 1;
+            for (uint32_t y = t; y < W; ++y) fresh_after &= !l.lut[a.in[y]];
+          }
+        }
+      }
+      bc[3] = fresh_after;
+    }
+    __syncthreads();
+    // ---- emit the windows starting in [S, E)
+    if (bc[2]) {
+      const uint32_t Pc = bc[1], fresh_after = bc[3];
+      const uint32_t last = llnz[kChunkLanes - 1], E = le[last];
+      const uint32_t i_lo = win_from(S, mis0), i_hi = E >= a.n ? nwin : win_from(E, mis0);
+      const uint32_t nt = (i_hi - i_lo + 63) / 64;
+      const uint32_t per = (nt + kWinWaves - 1) / kWinWaves;
+      const uint32_t t_lo = min(nt, wid * per), t_hi = min(nt, t_lo + per);
+      if (t_lo < t_hi) {  // wave-uniform
+        auto meta = [&](uint32_t t) {
+          return group_meta(a, g, i_lo + t * 64 + lane, i_hi, c0, last, Pc, mis0, fresh_after, cap);
+        };
+        auto wpos = [&](uint32_t t) { return (int64_t)(i_lo + t * 64 + lane) * kWin - mis0; };
+        auto is_edge = [&](uint32_t t) { return i_lo + t * 64 == 0 || i_lo + t * 64 + 64 >= nwin; };
+        WinMeta cur = meta(t_lo), nxt = meta(t_lo + 1);
+        Win64 dat = is_edge(t_lo) ? win_load<true>(a.in, wpos(t_lo), a.n) : win_load<false>(a.in, wpos(t_lo), a.n);
+        for (uint32_t t = t_lo; t < t_hi; ++t) {
+          const uint32_t i = i_lo + t * 64 + lane;
+          Win64 ndat = dat;
+          if (t + 1 < t_hi)
+            ndat = is_edge(t + 1) ? win_load<true>(a.in, wpos(t + 1), a.n) : win_load<false>(a.in, wpos(t + 1), a.n);
+          const WinMeta n2 = meta(t + 2);
+          const uint32_t o_first = __shfl(cur.out, 0), o_next = __shfl(nxt.out, 0);
+          const uint32_t down = __shfl_down(cur.out, 1), fdown = __shfl_down(cur.fresh, 1);
+          const uint32_t f_next = __shfl(nxt.fresh, 0);
+          const uint32_t P = __shfl(cur.tok, 0);
+          // the group's last tile ends past E: its outputs are counted by the walk, within a
+          // bound (the last window ends at most 64 tokens and finishes one)
+          const bool exact = t + 1 < nt;
+          const uint32_t lastv = min(63u, i_hi - 1 - (i_lo + t * 64));
+          const uint32_t o_end = exact ? o_next : __shfl(cur.out, lastv) + 65;
+          const uint32_t span_end = (uint32_t)min<uint64_t>((uint64_t)(i_lo + t * 64 + 64) * kWin - mis0, a.n);
+          win_tile(tb, a, stage, lane, cur, i, i < i_hi, is_edge(t), dat, wpos(t), nwin, o_first, o_end, exact,
+                   lane < 63 ? down : o_next, lane < 63 ? fdown : f_next, P, span_end, cap);
+          cur = nxt;
+          nxt = n2;
+          dat = ndat;
+        }
+      }
+    }
+    __syncthreads();  // the group's LDS is rewritten by the next one
+  }
+}
+
+__global__ void k_onepass_reset(uint64_t *st, uint32_t n, uint32_t *ctr) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) st[i] = 0;
+  if (i == 0) *ctr = 0;
+}
 
 // ------------------------------------------------------------- B. batched documents
 // Many documents, each with its own (lexer, mode) instance, in one sequence of launches
@@ -1653,17 +2043,21 @@ static size_t carve_layout(uint32_t n, uint32_t lane_bytes, uint32_t block, int 
   at += align256((size_t)nlanes * 4);
   offs[14] = at;  // per workgroup: last non-empty lane
   at += align256((size_t)nblocks * 4);
+  offs[15] = at;  // one pass: look-back status per workgroup
+  if (windowed) at += align256((size_t)nblocks * 8);
+  offs[16] = at;  // one pass: workgroup counter
+  if (windowed) at += align256(4);
   return at;
 }
 
 size_t workspace_bytes(uint32_t n, uint32_t lane_bytes, uint32_t block, int pipeline, int windowed) {
-  size_t offs[15];
+  size_t offs[17];
   return carve_layout(n, lane_bytes, block, pipeline, windowed, offs);
 }
 
 bool carve(void *ws, size_t ws_bytes, uint32_t n, uint32_t lane_bytes, uint32_t block, int pipeline, int windowed,
            Plan &p) {
-  size_t offs[15];
+  size_t offs[17];
   const size_t need = carve_layout(n, lane_bytes, block, pipeline, windowed, offs);
   if (ws_bytes < need || !ws) return false;
   uint8_t *b = static_cast<uint8_t *>(ws);
@@ -1691,11 +2085,14 @@ bool carve(void *ws, size_t ws_bytes, uint32_t n, uint32_t lane_bytes, uint32_t 
   p.ck_over = windowed ? reinterpret_cast<uint2 *>(b + offs[12] + align256((size_t)p.kslots * p.nlanes * 8)) : nullptr;
   p.lnz = reinterpret_cast<int32_t *>(b + offs[13]);
   p.blk_lnz = reinterpret_cast<int32_t *>(b + offs[14]);
+  p.chunk_st = windowed ? reinterpret_cast<uint64_t *>(b + offs[15]) : nullptr;
+  p.chunk_ctr = windowed ? reinterpret_cast<uint32_t *>(b + offs[16]) : nullptr;
   return true;
 }
 
 size_t walk_lds_bytes(int nrows, uint32_t block, bool emit) { return lds_bytes(nrows, (int)block, emit); }
 size_t window_lds_bytes(int nrows) { return win_lds_bytes(nrows); }
+size_t onepass_lds_bytes(int nrows) { return one_lds_bytes(nrows); }
 
 static CertArg cert_arg(const CertMap &cm) {
   CertArg ca{};
@@ -1744,6 +2141,8 @@ static WalkArgs walk_args(const DevTable &t, const CertMap &cm, const uint8_t *i
   a.kslots = p.kslots;
   a.lnz = p.lnz;
   a.blk_lnz = p.blk_lnz;
+  a.chunk_st = p.chunk_st;
+  a.chunk_ctr = p.chunk_ctr;
   a.block = p.block;
   a.block_shift = (uint32_t)__builtin_ctz(p.block);
   {
@@ -1950,6 +2349,40 @@ hipError_t run_fused(const DevTable &t, const CertMap &cm, const uint8_t *cert_l
   if (one && p.nlanes != 1) return hipErrorInvalidValue;
   const WalkArgs a = walk_args(t, cm, in, p, kinds, lens, offs, cap, res, cert_lut);
   return count_scan_emit<true>(t, a, p, cap, res, s, ev);
+}
+
+hipError_t run_onepass(const DevTable &t, const CertMap &cm, const uint8_t *cert_lut, const uint8_t *in,
+                       const Plan &p, bool serial, uint8_t *kinds, uint32_t *lens, uint64_t *offs, uint64_t cap,
+                       ResultDev *res, hipStream_t s, hipEvent_t const *ev) {
+  const bool one = serial || p.nlanes == 1 || cm.nbytes == 0;
+  if (one && p.nlanes != 1) return hipErrorInvalidValue;
+  if (p.block != kChunkLanes || !p.windowed || !t.monotone || !p.chunk_st) return hipErrorInvalidValue;
+  const size_t lds = one_lds_bytes(t.nrows);
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  WalkArgs a = walk_args(t, cm, in, p, kinds, lens, offs, cap, res, cert_lut);
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  const uint32_t per_cu = std::max<uint32_t>(1, std::min<uint32_t>(8, (uint32_t)(160 * 1024 / lds)));
+  const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>(p.nblocks, (uint32_t)cus * per_cu));
+  mark(ev, 0, s);
+  k_onepass_reset<<<(p.nblocks + 255) / 256, 256, 0, s>>>(p.chunk_st, p.nblocks, p.chunk_ctr);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  mark(ev, 1, s);
+  k_onepass<<<grid, kChunkLanes, lds, s>>>(a);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  mark(ev, 2, s);
+  k_scan<<<1, 1024, 0, s>>>(p.blk_sum, p.blk_fail, p.blk_nonempty, p.blk_big, p.blk_lnz, p.nblocks, p.block,
+                            p.counts, p.meta, res, cap, p.n);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  mark(ev, 3, s);
+  a.fallback_only = 1;  // halted scans, long slices, an unfinished look-back
+  k_emit<true, true><<<p.nblocks, p.block, lds_bytes(t.nrows, (int)p.block, true), s>>>(a);
+  e = hipGetLastError();
+  mark(ev, 4, s);
+  return e;
 }
 
 }  // namespace lexk

@@ -144,17 +144,20 @@ int finish_compile(lex_dfa *d, lex_dfa **out, char *err, size_t errlen) {
 struct Resolved {
   uint32_t lane_bytes;
   uint32_t block;
-  int path;  // 1 pipeline, 2 fused
+  int path;  // 1 pipeline, 2 fused (one pass or separate launches)
   bool serial;
   int table;  // 0 exact, 1 discard
   bool windowed;
+  bool onepass;  // fused, in one pass
 };
 
-uint32_t default_lane_bytes(uint64_t n) {
-  // Aim for about 512k lanes (2048 resident lanes on each of 256 CUs), between 64 B
-  // and 4 KiB.
+uint32_t default_lane_bytes(uint64_t n, bool onepass) {
+  // Aim for about 512k lanes (2048 resident lanes on each of 256 CUs), or in one pass
+  // about 256k (one 256-lane group for each of the ~1024 resident one-pass workgroups),
+  // between 64 B and 4 KiB.
+  const uint64_t want = onepass ? 256u << 10 : 512u << 10;
   uint64_t l = 64;
-  while (l < 4096 && n / l > (512u << 10)) l <<= 1;
+  while (l < 4096 && n / l > want) l <<= 1;
   return (uint32_t)l;
 }
 
@@ -169,16 +172,23 @@ int resolve(const lex_dfa *d, uint64_t n, int mode, const lex_run_opts *o, Resol
   if (mode < 0 || mode > 3) return LEX_EINVAL;
   r.table = mode & 1;
   r.serial = (mode & 2) != 0 || d->cm[r.table].nbytes == 0;
-  r.path = o && o->path ? o->path : 2;  // fused planning by default
-  if (r.path != 1 && r.path != 2) return LEX_EINVAL;
-  r.block = o && o->block_threads ? (uint32_t)o->block_threads : default_block(d->c.nrows);
+  const int asked = o && o->path ? o->path : 0;
+  if (asked < 0 || asked > 3) return LEX_EINVAL;
+  const int32_t bt = o ? o->block_threads : 0;
+  if (asked == 3 && bt && bt != (int32_t)lexk::kChunkLanes) return LEX_EINVAL;
   const int emit = o ? o->emit : LEX_EMIT_DEFAULT;
   if (emit != LEX_EMIT_DEFAULT && emit != LEX_EMIT_LANE) return LEX_EINVAL;
   r.windowed = emit == LEX_EMIT_DEFAULT && d->c.monotone && d->all_counted[r.table] && d->c.nrows <= 256 &&
                lexk::window_lds_bytes(d->c.nrows) <= 160 * 1024;
+  // By default (and as path 3) a windowed scan runs in one pass when its workgroup fits;
+  // every other scan takes the fused path unless the pipeline is asked for.
+  r.onepass = (asked == 0 || asked == 3) && r.windowed && (!bt || bt == (int32_t)lexk::kChunkLanes) &&
+              lexk::onepass_lds_bytes(d->c.nrows) <= 160 * 1024;
+  r.path = asked == 1 ? 1 : 2;
+  r.block = r.onepass ? lexk::kChunkLanes : bt ? (uint32_t)bt : default_block(d->c.nrows);
   if (r.block != 256u && r.block != 512u && r.block != 1024u) return LEX_EINVAL;
   if (lexk::walk_lds_bytes(d->c.nrows, r.block, true) > 160 * 1024) return LEX_ELIMIT;
-  uint32_t lb = o && o->lane_bytes ? o->lane_bytes : default_lane_bytes(n);
+  uint32_t lb = o && o->lane_bytes ? o->lane_bytes : default_lane_bytes(n, r.onepass);
   if (lb < 16 || (lb & 15)) return LEX_EINVAL;
   if (o && o->chunk_bytes) {
     if (o->chunk_bytes % lb) return LEX_EINVAL;  // lanes subdivide the paper's chunks
@@ -288,6 +298,19 @@ size_t lex_workspace_size(const lex_dfa *d, uint64_t n, int mode, const lex_run_
   return lexk::workspace_bytes((uint32_t)n, r.lane_bytes, r.block, r.path == 1, r.windowed);
 }
 
+int lex_plan(const lex_dfa *d, uint64_t n, int mode, const lex_run_opts *opts, lex_plan_info *out) {
+  if (!d || !out) return LEX_EINVAL;
+  if (n > 0xFFFFFFF0ull) return LEX_ELIMIT;
+  Resolved r;
+  const int rc = resolve(d, n, mode, opts, r);
+  if (rc != LEX_OK) return rc;
+  out->lane_bytes = r.lane_bytes;
+  out->block_threads = r.block;
+  out->path = r.onepass ? 3 : r.path;
+  out->windowed = r.windowed ? 1 : 0;
+  return LEX_OK;
+}
+
 int lex_run(const lex_dfa *d, const uint8_t *d_bytes, uint64_t n, int mode, uint8_t *d_kinds, uint32_t *d_lens,
             uint64_t *d_offsets, uint64_t cap, lex_result *d_result, void *d_ws, size_t ws_bytes,
             const lex_run_opts *opts, void *stream) {
@@ -310,8 +333,10 @@ int lex_run(const lex_dfa *d, const uint8_t *d_bytes, uint64_t n, int mode, uint
   hipStream_t s = static_cast<hipStream_t>(stream);
   auto *res = reinterpret_cast<lexk::ResultDev *>(d_result);
   hipEvent_t const *ev = opts && opts->events ? reinterpret_cast<hipEvent_t const *>(opts->events) : nullptr;
-  hipError_t e = r.path == 1 ? lexk::run_pipeline(t, d->cm[m], d_bytes, p, r.serial, d_kinds, d_lens, d_offsets,
-                                                  cap, res, s, ev)
+  hipError_t e = r.path == 1   ? lexk::run_pipeline(t, d->cm[m], d_bytes, p, r.serial, d_kinds, d_lens, d_offsets,
+                                                    cap, res, s, ev)
+                 : r.onepass ? lexk::run_onepass(t, d->cm[m], dc->d_cert_lut[m], d_bytes, p, r.serial, d_kinds,
+                                                 d_lens, d_offsets, cap, res, s, ev)
                              : lexk::run_fused(t, d->cm[m], dc->d_cert_lut[m], d_bytes, p, r.serial, d_kinds,
                                                d_lens, d_offsets, cap, res, s, ev);
   return e == hipSuccess ? LEX_OK : LEX_EDEVICE;

@@ -123,6 +123,13 @@ class Lexer:
                                        nrows))
         return t, ri, rk
 
+    def plan(self, n: int, mode: int = abi.LEX_MODE_EXACT, opts: abi.RunOpts | None = None) -> dict:
+        """The configuration a scan of n bytes would use: lane_bytes, block_threads, path
+        (1 pipeline, 2 fused, 3 one pass) and windowed."""
+        out = abi.PlanInfo()
+        abi.check(abi.lib().lex_plan(self._h, n, mode, C.byref(opts) if opts else None, C.byref(out)), "lex_plan")
+        return {k: getattr(out, k) for k, _ in abi.PlanInfo._fields_}
+
     def workspace_size(self, n: int, mode: int, opts: abi.RunOpts | None = None) -> int:
         ws = abi.lib().lex_workspace_size(self._h, n, mode, C.byref(opts) if opts else None)
         if ws == 0:

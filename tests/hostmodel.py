@@ -134,7 +134,7 @@ def windowed(model, w: bytes, starts, ends, lane: int, base: int, block: int = 4
     input's address modulo W.  block: lanes per count workgroup.  Returns (kinds, lens, offs),
     or None when a slice halts (the library then uses the lane emit).  Mirrors the kernels'
     bookkeeping: window checkpoints, owner lookup through the last-non-empty-lane prefixes,
-    64-window tiles, the staged words (end - P) << 8 | kind with the 4-slot padding, and the
+    64-window tiles, the staged words (end - P) << 8 | kind after 4 to 7 padding slots, and the
     direct fallback for ranges longer than the stage.
     """
     T, info, kind = model.T, model.info, model.kind
@@ -207,10 +207,10 @@ def windowed(model, w: bytes, starts, ends, lane: int, base: int, block: int = 4
         last = min(63, nwin - 1 - tile * 64)
         o_end = nxt[last][2]
         P = ms[0][1]
-        total, pad = o_end - o_first, o_first & 3
+        total, pad = o_end - o_first, (o_first & 3) + 4
         span_end = min((tile + 1) * 64 * W - mis0, n)
         staged = o_first <= o_end <= ntok and total + pad + 3 <= stage_words - 64 and span_end - P < (1 << 24)
-        stage = {}
+        stage = {pad - 1: 0}  # the end before the tile's first token: 0 relative to P
         for L, i in enumerate(ids):
             if i >= nwin:
                 continue
@@ -242,13 +242,10 @@ def windowed(model, w: bytes, starts, ends, lane: int, base: int, block: int = 4
         if not staged:
             continue
         o0 = o_first - pad
-        for q in range(0, pad + total, 4):
-            prev = stage[q - 1] >> 8 if q > pad else 0
+        for q in range(4, pad + total, 4):
+            ev = [stage.get(g, 0) >> 8 for g in range(q - 1, q + 4)]
             for k in range(4):
                 g = q + k
-                endp = stage.get(g, 0) >> 8
-                pv = prev if g > pad else 0
                 if pad <= g < pad + total:
-                    kinds[o0 + g], lens[o0 + g], offs[o0 + g] = stage[g] & 0xFF, endp - pv, P + pv
-                prev = endp
+                    kinds[o0 + g], lens[o0 + g], offs[o0 + g] = stage[g] & 0xFF, ev[k + 1] - ev[k], P + ev[k]
     return kinds, lens, offs

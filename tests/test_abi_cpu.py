@@ -51,6 +51,29 @@ def test_host_side_argument_checks():
     assert lx.workspace_size(1 << 20, 0) > 0
 
 
+def test_plan_query():
+    """lex_plan reports what lex_run would use: one pass by default where the windowed emit
+    applies (256-lane workgroups), the fused path otherwise, the pipeline when asked."""
+    cl = P.Lexer.compile(T.as_tuples(T.CLIKE_L))
+    js = P.Lexer.compile(T.as_tuples(T.JSON))
+    d = cl.plan(512 << 20)
+    assert d == {"lane_bytes": 2048, "block_threads": 256, "path": 3, "windowed": 1}
+    assert cl.plan(512 << 20, opts=P.RunOpts(path=2))["lane_bytes"] == 1024
+    assert cl.plan(512 << 20, opts=P.RunOpts(path=2))["path"] == 2
+    assert cl.plan(512 << 20, opts=P.RunOpts(path=1))["path"] == 1
+    assert cl.plan(512 << 20, opts=P.RunOpts(emit=P.LEX_EMIT_LANE)) ["path"] == 2
+    assert cl.plan(512 << 20, opts=P.RunOpts(block_threads=1024))["path"] == 2  # default path, other block
+    j = js.plan(256 << 20, P.LEX_MODE_DISCARD)  # not monotone: no windowed emit, no one pass
+    assert j["path"] == 2 and j["windowed"] == 0
+    assert js.plan(256 << 20, P.LEX_MODE_DISCARD, P.RunOpts(path=3))["path"] == 2
+    with pytest.raises(P.LexError):
+        cl.plan(1 << 20, opts=P.RunOpts(path=3, block_threads=1024))  # one pass uses 256
+    with pytest.raises(P.LexError):
+        cl.plan(1 << 20, opts=P.RunOpts(path=4))
+    with pytest.raises(P.LexError):
+        cl.plan(1 << 33)
+
+
 def test_info_and_tables():
     lx = P.Lexer.compile(T.as_tuples(T.JSON))
     info = lx.info()

@@ -71,14 +71,14 @@ CL = workloads.clike(1 << 20, 1)  # the 1 MiB config, seed 1
 
 
 @pytest.mark.parametrize("emit", [P.LEX_EMIT_DEFAULT, P.LEX_EMIT_LANE])
-@pytest.mark.parametrize("path", [1, 2])
+@pytest.mark.parametrize("path", [1, 2, 3])
 @pytest.mark.parametrize("lane", [16, 48, 64, 256, 1024, 4096, 0])
 def test_clike_1mib_exact(path, lane, emit):
     r = check("clike_l", CL, P.LEX_MODE_EXACT, opts(lane, path, emit))
     assert r.nslices > 1
 
 
-@pytest.mark.parametrize("path", [1, 2])
+@pytest.mark.parametrize("path", [1, 2, 3])
 def test_windowed_dense_tokens_direct(path):
     """One-byte tokens: every wave's output range outgrows its LDS stage, so the windowed
     emit writes token by token."""
@@ -96,19 +96,83 @@ def test_windowed_lane_starts_on_tile_boundaries(pad):
     b[4096::4096] = ord("\n")
     b[4096 * 3 - 1] = ord("\n")  # and one just before a boundary
     for lane in (64, 1024, 4096):
-        for path in (1, 2):
+        for path in (1, 2, 3):
             check("clike_l", b, P.LEX_MODE_EXACT, opts(lane, path), pad_front=pad)
 
 
 def test_windowed_long_slice_falls_back():
-    """A slice of 2^24 bytes or more (one 17 MiB comment) keeps no checkpoints: the lane
-    emit takes the scan."""
+    """A slice of 2^24 bytes or more (one 17 MiB comment): its checkpoints cannot hold its
+    counts, so the lane emit takes the scan (after the one-pass kernel, its fallback)."""
     big = np.concatenate([CL[:5000], np.frombuffer(b"// ", np.uint8),
                           np.full(17 << 20, ord("c"), np.uint8), np.frombuffer(b"\n", np.uint8), CL[:7000]])
-    check("clike_l", big, P.LEX_MODE_EXACT, opts(1024, 2), offsets=False)
+    for path in (2, 3):
+        check("clike_l", big, P.LEX_MODE_EXACT, opts(1024, path), offsets=False)
 
 
-@pytest.mark.parametrize("path", [1, 2])
+def sparse_lf(buf, keep_every, seed):
+    """buf with most LFs (the only certified byte of C-like-L) turned into spaces: one in
+    keep_every stays, so lanes often hold none and slices run across many lanes."""
+    b = np.array(buf, copy=True)
+    lf = np.flatnonzero(b == 10)
+    rng = np.random.default_rng(seed)
+    b[lf[rng.random(lf.size) >= 1.0 / keep_every]] = 32
+    return b
+
+
+def no_comments(buf):
+    """buf with every line comment blanked to spaces (so that removing LFs later does not
+    turn the following lines into comment text)."""
+    _, oc = lexers("clike_l")
+    kinds, lens, offs, _ = oc.lex(bytes(buf), offsets=True)
+    lc = [i for i, d in enumerate(T.CLIKE_L) if d.name == "LCOMMENT"]
+    b = np.array(buf, copy=True)
+    sel = np.isin(kinds, lc)
+    for o, n in zip(offs[sel], lens[sel]):
+        b[o:o + n] = 32
+    return b
+
+
+def lf_at(buf, positions):
+    """buf with an LF at each given position that lies inside an IDENT, INT or SPACE token
+    of the oracle's scan (there an LF only splits the token and the input stays lexable; in
+    a string, a comment or a two-byte operator it would not); returns the buffer and how
+    many were placed."""
+    _, oc = lexers("clike_l")
+    kinds, lens, offs, _ = oc.lex(bytes(buf), offsets=True)
+    safe = [i for i, d in enumerate(T.CLIKE_L) if d.name in ("IDENT", "INT", "SPACE")]
+    ok = np.zeros(len(buf), bool)
+    sel = np.isin(kinds, safe)
+    for o, n in zip(offs[sel], lens[sel]):
+        ok[o:o + n] = True
+    b = np.array(buf, copy=True)
+    placed = 0
+    for x in positions:
+        if 0 < x < b.size and ok[x]:
+            b[x] = 10
+            placed += 1
+    return b, placed
+
+
+@pytest.mark.parametrize("path", [1, 2, 3])
+@pytest.mark.parametrize("lane", [128, 256, 1024])
+def test_planner_edges(path, lane):
+    """The fused planner's cases: lanes without a certified byte (empty slices), slices
+    across many lanes, certified bytes exactly at lane targets and at 128-byte line
+    boundaries, a slice ending at a lane target; aligned and unaligned buffers."""
+    base = CL[:300000]
+    for label, buf in [("sparse 1/60", sparse_lf(base, 60, 1)), ("sparse 1/400", sparse_lf(base, 400, 2)),
+                       ("no LF", sparse_lf(base[:20000], 10 ** 9, 3))]:
+        for pad in (0, 5, 77):
+            check("clike_l", buf, P.LEX_MODE_EXACT, opts(lane, path), pad_front=pad, label=label)
+    sp = sparse_lf(no_comments(base), 200, 4)
+    at = [j * lane + d for j in range(1, sp.size // lane) for d in (-1, 0, 1, 127, 128)]
+    at_buf, placed = lf_at(sp, at)
+    assert placed > sp.size // lane
+    for pad in (0, 64, 3):
+        check("clike_l", at_buf, P.LEX_MODE_EXACT, opts(lane, path), pad_front=pad, label="LF at targets")
+
+
+@pytest.mark.parametrize("path", [1, 2, 3])
 def test_clike_ragged_and_unaligned(path):
     for n in (1, 15, 16, 17, 63, 64, 65, 4095, 4097, 70001):
         for pad in (0, 3):
@@ -129,7 +193,7 @@ def _stray(buf, k, seed):
     return b
 
 
-@pytest.mark.parametrize("path", [1, 2])
+@pytest.mark.parametrize("path", [1, 2, 3])
 def test_malformed_error_offset(path):
     """Corollary 1: output truncated at the first halting slice, error offset = con(w)."""
     base = CL[:300000]
@@ -142,13 +206,13 @@ def test_malformed_error_offset(path):
         check("clike_l", buf, P.LEX_MODE_EXACT, opts(64, path))
 
 
-@pytest.mark.parametrize("path", [1, 2])
+@pytest.mark.parametrize("path", [1, 2, 3])
 def test_discard_clike_d(path):
     check("clike_d", CL, P.LEX_MODE_DISCARD, opts(256, path))
     check("clike_d", CL, P.LEX_MODE_EXACT, opts(256, path))  # empty exact map: one slice
 
 
-@pytest.mark.parametrize("path", [1, 2])
+@pytest.mark.parametrize("path", [1, 2, 3])
 def test_json_discard(path):
     js = workloads.json(2 << 20, 4)
     r = check("json", js, P.LEX_MODE_DISCARD, opts(128, path))
