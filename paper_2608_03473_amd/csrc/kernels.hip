@@ -1649,7 +1649,24 @@ __global__ void k_onepass_reset(uint64_t *st, uint32_t n, uint32_t *ctr) {
 // and emit workgroups pull 64-lane tiles from atomic queues (work stealing).  Each
 // document's result is its own scan's: its tokens up to and including its first halted
 // slice, error offset relative to the document.
+//
+// Hybrid plan for refused token sets: a document of such a set (no useful certified byte),
+// not flagged serial and longer than one speculative lane (kSpecLane bytes, or lane_bytes if
+// larger) is split speculatively.  Lane k starts at k * S in the start row as if a token
+// began there, walks its range and kSpecX bytes on, and restarts one byte further on after
+// a halt, recording the token starts of its first kSpecX bytes (head) and of the kSpecX
+// bytes after its range (tail).  Lane 0 is the serial scan.  If lane k - 1's walk is the
+// serial scan by the end of its range, the first position where its tail and lane k's head
+// both start a token is a token start of the serial scan, and from there both walks agree
+// (both restart in the start row on the same bytes).  By induction the cuts found this
+// way are serial token boundaries, and the slices between them are counted and emitted
+// like certified slices.  A document falls back to one lane when a boundary finds no common
+// start within kSpecX bytes, or when a lane restarted at or after its own cut (the serial
+// scan halts there: the one-lane scan then reports the error as usual).
 constexpr int kMaxInst = 8;
+constexpr uint32_t kSpecLane = 4096;
+constexpr uint32_t kSpecX = 512;
+constexpr uint32_t kSpecWords = kSpecX / 32;
 
 struct BatchInst {
   uint32_t start, sink, fail;  // row byte offsets in the combined table
@@ -1669,7 +1686,7 @@ struct DocResDev {  // mirrors lex_doc_result
   uint32_t nslices;
 };
 
-enum { kQCount = 0, kQEmit = 1, kNLanes = 2, kBad = 3, kBatchMeta = 4 };
+enum { kQCount = 0, kQEmit = 1, kNLanes = 2, kBad = 3, kNSpec = 4, kBatchMeta = 8 };
 
 struct BatchArgs {
   const uint32_t *table;
@@ -1684,6 +1701,10 @@ struct BatchArgs {
   uint32_t *meta;  // kBatchMeta words: queues, lane count
   uint32_t *lanes_of, *lane_base, *lane_doc, *cuts, *ends, *counts, *halted, *lane_pre, *doc_halt;
   uint32_t *doc_ntok, *doc_nsl;
+  // hybrid plan: per document the first speculative lane's index and the fall-back flag;
+  // per speculative lane its document, cut, last restart, and head then tail token starts
+  uint32_t spec_bytes, max_spec;
+  uint32_t *spec_base, *spec_fail, *spec_doc, *spec_cut, *spec_rst, *spec_bits;
   uint8_t *kinds;
   uint32_t *lens;
   uint64_t *offs;
@@ -1719,9 +1740,19 @@ __device__ __forceinline__ BatchLds batch_stage(const BatchArgs &a) {
   return BatchLds{lds_bytes_of(smem), info, kind, luts, smem + batch_lds_offset(a.nrows, a.ninst)};
 }
 
+__device__ __forceinline__ bool spec_split(const BatchArgs &a, const DocDev &d) {
+  return d.inst < a.ninst && a.inst[d.inst].refused && !(d.flags & 1) && d.length > a.spec_bytes;
+}
+
 __device__ __forceinline__ bool one_lane(const BatchArgs &a, const DocDev &d) {
   // (an unknown instance stops the batch; it is never looked up)
-  return d.length <= a.lane_bytes || (d.flags & 1) || d.inst >= a.ninst || a.inst[d.inst].refused;
+  return !spec_split(a, d) &&
+         (d.length <= a.lane_bytes || (d.flags & 1) || d.inst >= a.ninst || a.inst[d.inst].refused);
+}
+
+__device__ __forceinline__ uint32_t doc_lanes(const BatchArgs &a, const DocDev &d) {
+  if (spec_split(a, d)) return (uint32_t)(((uint64_t)d.length + a.spec_bytes - 1) / a.spec_bytes);
+  return one_lane(a, d) ? 1 : (uint32_t)(((uint64_t)d.length + a.lane_bytes - 1) / a.lane_bytes);
 }
 
 // One workgroup: lanes per document, lane numbering (long single-lane documents first),
@@ -1750,7 +1781,7 @@ __global__ void __launch_bounds__(1024) k_bplan(BatchArgs a) {
     uint64_t sum = 0;
     for (uint32_t d = lo; d < hi; ++d) {
       const DocDev doc = a.docs[d];
-      const uint32_t nl = one_lane(a, doc) ? 1 : (uint32_t)(((uint64_t)doc.length + a.lane_bytes - 1) / a.lane_bytes);
+      const uint32_t nl = doc_lanes(a, doc);
       const bool first = nl == 1 && doc.length > a.lane_bytes;
       if (group == 0) a.lanes_of[d] = nl;
       if (first == (group == 0)) sum += nl;
@@ -1775,10 +1806,30 @@ __global__ void __launch_bounds__(1024) k_bplan(BatchArgs a) {
     base += part[nt - 1];
     __syncthreads();
   }
+  // speculative lanes: numbered per document, in document order
+  uint64_t sum = 0;
+  for (uint32_t d = lo; d < hi; ++d) {
+    a.spec_fail[d] = 0;
+    if (spec_split(a, a.docs[d])) sum += a.lanes_of[d];
+  }
+  part[tid] = sum;
+  __syncthreads();
+  for (uint32_t d = 1; d < nt; d <<= 1) {
+    const uint64_t v = tid >= d ? part[tid - d] : 0;
+    __syncthreads();
+    part[tid] += v;
+    __syncthreads();
+  }
+  uint64_t run = tid ? part[tid - 1] : 0;
+  for (uint32_t d = lo; d < hi; ++d) {
+    a.spec_base[d] = (uint32_t)min<uint64_t>(run, 0xFFFFFFFFu);
+    if (spec_split(a, a.docs[d])) run += a.lanes_of[d];
+  }
   if (tid == 0) {
-    const bool stop = bad || base > a.max_lanes;
+    const bool stop = bad || base > a.max_lanes || part[nt - 1] > a.max_spec;
     a.meta[kBad] = stop;
     a.meta[kNLanes] = stop ? 0 : (uint32_t)base;
+    a.meta[kNSpec] = stop ? 0 : (uint32_t)part[nt - 1];
   }
 }
 
@@ -1790,6 +1841,129 @@ __global__ void __launch_bounds__(256) k_bmap(BatchArgs a) {
   for (uint32_t d = wave; d < a.ndocs; d += nwaves) {
     const uint32_t lb = a.lane_base[d], nl = a.lanes_of[d];
     for (uint32_t k = lane; k < nl; k += 64) a.lane_doc[lb + k] = d;
+    if (spec_split(a, a.docs[d]))
+      for (uint32_t k = lane; k < nl; k += 64) a.spec_doc[a.spec_base[d] + k] = d;
+  }
+}
+
+// Speculative walk of [b, end) (hybrid plan): from the start row as if a token began at b,
+// restarting one byte further on after a halt (a halt at the start of a token that cannot
+// be matched), so the walk never stops.  Token starts in [b, b + kSpecX) go to head, those
+// in [b2, b2 + kSpecX) to tail (bit i: position base + i); rst: the last restart position
+// or kNone.  Token starts come in increasing order, so each bitmap is built a word at a
+// time.  Bytes are read through a 16-byte block held in registers.
+template <bool MONO>
+__device__ void walk_spec(const Tables &tb, const uint8_t *in, uint32_t n, uint32_t b, uint32_t end, uint32_t b2,
+                          uint32_t *head, uint32_t *tail, uint32_t &rst) {
+  uint32_t hw = 0, hv = 0, tw = 0, tv = 0;  // current word index and bits of head and tail
+  auto mark = [&](uint32_t t) {
+    if (t - b < kSpecX) {
+      const uint32_t w = (t - b) >> 5;
+      if (w != hw) {
+        head[hw] = hv;
+        hw = w;
+        hv = 0;
+      }
+      hv |= 1u << ((t - b) & 31);
+    }
+    if (t - b2 < kSpecX) {
+      const uint32_t w = (t - b2) >> 5;
+      if (w != tw) {
+        tail[tw] = tv;
+        tw = w;
+        tv = 0;
+      }
+      tv |= 1u << ((t - b2) & 31);
+    }
+  };
+  for (uint32_t w = 0; w < kSpecWords; ++w) head[w] = tail[w] = 0;
+  const uintptr_t base = reinterpret_cast<uintptr_t>(in);
+  int64_t cb = INT64_MIN;  // position of the cached block (16-aligned in memory)
+  uint4 cv = make_uint4(0, 0, 0, 0);
+  uint32_t st = tb.start, tok = b, lacc = b;
+  rst = kNone;
+  mark(b);
+  for (uint32_t p = b; p < end;) {
+    const int64_t blk = (int64_t)p - (int64_t)((base + p) & 15);
+    if (blk != cb) {
+      cb = blk;
+      cv = load_block(in, blk, n);
+    }
+    const uint32_t q = (uint32_t)((int64_t)p - blk);
+    const uint32_t w4 = q < 4 ? cv.x : q < 8 ? cv.y : q < 12 ? cv.z : cv.w;
+    const uint32_t e = entry(tb, st, (w4 >> (8 * (q & 3))) & 0xFFu);
+    if (e & kEmitBit) {
+      tok = p;
+      mark(p);
+    }
+    st = e & kRowMask;
+    if (!MONO && (e & kAccBit)) lacc = p + 1;
+    ++p;
+    if (st == tb.sink || (!MONO && st == tb.fail)) {
+      if (!MONO && st == tb.fail && lacc > tok) {
+        tok = lacc;  // longest match: the token ends at its last accepting position
+      } else {
+        rst = tok;  // no token starts at tok: restart one byte on
+        tok = tok + 1;
+      }
+      p = tok;
+      lacc = tok;
+      st = tb.start;
+      if (p < end) mark(p);
+    }
+  }
+  head[hw] = hv;
+  tail[tw] = tv;
+}
+
+// Speculative walks: one thread per speculative lane.
+__global__ void __launch_bounds__(256) k_bspec(BatchArgs a) {
+  const BatchLds l = batch_stage(a);
+  if (a.meta[kBad]) return;
+  const uint32_t ns = a.meta[kNSpec];
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < ns; i += gridDim.x * blockDim.x) {
+    const uint32_t d = a.spec_doc[i];
+    const DocDev doc = a.docs[d];
+    const BatchInst &in = a.inst[doc.inst];
+    const uint32_t k = i - a.spec_base[d], S = a.spec_bytes;
+    const uint32_t b = k * S;  // < length
+    // the tail window; past the document's end it can hold no token start
+    const uint32_t b2 = (uint32_t)min<uint64_t>((uint64_t)(k + 1) * S, doc.length);
+    const uint32_t end = (uint32_t)min<uint64_t>((uint64_t)b2 + kSpecX, doc.length);
+    const Tables tb{l.T, l.info, l.kind, in.sink, in.fail, in.start};
+    uint32_t *bits = a.spec_bits + (size_t)i * 2 * kSpecWords;
+    uint32_t rst;
+    if (in.mono) walk_spec<true>(tb, a.bytes + doc.offset, doc.length, b, end, b2, bits, bits + kSpecWords, rst);
+    else walk_spec<false>(tb, a.bytes + doc.offset, doc.length, b, end, b2, bits, bits + kSpecWords, rst);
+    a.spec_rst[i] = rst;
+  }
+}
+
+// Cuts of the hybrid plan: one thread per speculative lane k; lane k's cut is the first
+// common token start of lane k - 1's tail and lane k's head (lane 0: the document start).
+// A missing cut, or a restart at or after the lane's cut, sends the document to one lane.
+__global__ void __launch_bounds__(256) k_bsync(BatchArgs a) {
+  if (a.meta[kBad]) return;
+  const uint32_t ns = a.meta[kNSpec];
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < ns; i += gridDim.x * blockDim.x) {
+    const uint32_t d = a.spec_doc[i];
+    const uint32_t k = i - a.spec_base[d];
+    uint32_t cut = 0;
+    bool ok = true;
+    if (k) {
+      const uint32_t *head = a.spec_bits + (size_t)i * 2 * kSpecWords;
+      const uint32_t *tail = a.spec_bits + (size_t)(i - 1) * 2 * kSpecWords + kSpecWords;
+      cut = kNone;
+      for (uint32_t w = 0; w < kSpecWords && cut == kNone; ++w) {
+        const uint32_t x = head[w] & tail[w];
+        if (x) cut = k * a.spec_bytes + 32 * w + (__ffs(x) - 1);
+      }
+      ok = cut != kNone;
+    }
+    const uint32_t rst = a.spec_rst[i];
+    if (ok && rst != kNone && rst >= cut) ok = false;
+    a.spec_cut[i] = cut;
+    if (!ok) a.spec_fail[d] = 1;
   }
 }
 
@@ -1822,7 +1996,8 @@ __global__ void __launch_bounds__(256) k_bcount(BatchArgs a) {
     const BatchInst &in = a.inst[valid ? doc.inst : 0];
     const uint8_t *src = a.bytes + doc.offset;
     const uint8_t *lut = l.luts + 256 * (valid ? doc.inst : 0);
-    if (valid) {
+    const bool spec = valid && spec_split(a, doc);
+    if (valid && !spec) {
       if (jj == 0) start = 0;
       else start = search_cert(src, doc.length, in.ca, lut, jj * a.lane_bytes, a.lane_bytes, kNone);
     }
@@ -1831,7 +2006,16 @@ __global__ void __launch_bounds__(256) k_bcount(BatchArgs a) {
     if (!valid) continue;
     const bool same = lane < 63 && jj + 1 < nl;
     uint32_t s, e;
-    if (start == kNone) {
+    if (spec) {  // the hybrid plan's slice, or the whole document on one lane
+      const uint32_t i = a.spec_base[d] + jj;
+      if (a.spec_fail[d]) {
+        s = jj ? doc.length : 0;
+        e = doc.length;
+      } else {
+        s = a.spec_cut[i];
+        e = jj + 1 < nl ? a.spec_cut[i + 1] : doc.length;
+      }
+    } else if (start == kNone) {
       s = e = min(jj * a.lane_bytes, doc.length);
     } else {
       s = start;
@@ -2244,10 +2428,18 @@ static uint32_t batch_max_lanes(uint32_t ndocs, uint64_t nbytes, uint32_t lane_b
   return (uint32_t)std::min<uint64_t>(0xFFFFFFF0ull, (uint64_t)ndocs + nbytes / lane_bytes + 1);
 }
 
+static uint32_t batch_spec_bytes(uint32_t lane_bytes) { return std::max(kSpecLane, lane_bytes); }
+
+// speculative lanes: a split document of n bytes has ceil(n / S) <= n / S + 1 of them
+static uint32_t batch_max_spec(uint32_t ndocs, uint64_t nbytes, uint32_t lane_bytes) {
+  return (uint32_t)std::min<uint64_t>(0xFFFFFFF0ull, (uint64_t)ndocs + nbytes / batch_spec_bytes(lane_bytes) + 1);
+}
+
 size_t batch_workspace_bytes(uint32_t ndocs, uint64_t nbytes, uint32_t lane_bytes) {
   const uint64_t nl = batch_max_lanes(ndocs, nbytes, lane_bytes);
-  return align256(kBatchMeta * 4) + 5 * align256((size_t)std::max<uint32_t>(ndocs, 1) * 4) +
-         6 * align256((size_t)nl * 4);
+  const uint64_t ns = batch_max_spec(ndocs, nbytes, lane_bytes);
+  return align256(kBatchMeta * 4) + 7 * align256((size_t)std::max<uint32_t>(ndocs, 1) * 4) +
+         6 * align256((size_t)nl * 4) + 3 * align256((size_t)ns * 4) + align256((size_t)ns * 2 * kSpecWords * 4);
 }
 
 size_t batch_emit_lds_bytes(int nrows, uint32_t ninst) {
@@ -2292,6 +2484,15 @@ hipError_t run_batch(const BatchTables &bt, const uint8_t *bytes, uint64_t nbyte
   a.doc_halt = reinterpret_cast<uint32_t *>(w), w += dsz;
   a.doc_ntok = reinterpret_cast<uint32_t *>(w), w += dsz;
   a.doc_nsl = reinterpret_cast<uint32_t *>(w), w += dsz;
+  a.spec_base = reinterpret_cast<uint32_t *>(w), w += dsz;
+  a.spec_fail = reinterpret_cast<uint32_t *>(w), w += dsz;
+  a.spec_bytes = batch_spec_bytes(lane_bytes);
+  a.max_spec = batch_max_spec(ndocs, nbytes, lane_bytes);
+  const size_t per_spec = align256((size_t)a.max_spec * 4);
+  a.spec_doc = reinterpret_cast<uint32_t *>(w), w += per_spec;
+  a.spec_cut = reinterpret_cast<uint32_t *>(w), w += per_spec;
+  a.spec_rst = reinterpret_cast<uint32_t *>(w), w += per_spec;
+  a.spec_bits = reinterpret_cast<uint32_t *>(w), w += align256((size_t)a.max_spec * 2 * kSpecWords * 4);
   const size_t per_lane = align256((size_t)batch_max_lanes(ndocs, nbytes, lane_bytes) * 4);
   a.lane_doc = reinterpret_cast<uint32_t *>(w), w += per_lane;
   a.cuts = reinterpret_cast<uint32_t *>(w), w += per_lane;
@@ -2316,6 +2517,14 @@ hipError_t run_batch(const BatchTables &bt, const uint8_t *bytes, uint64_t nbyte
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) {
     k_bmap<<<gdoc, 256, 0, s>>>(a);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) {  // the hybrid plan's speculative walks and cuts
+    k_bspec<<<(uint32_t)cus * per_cu_c, 256, lds_c, s>>>(a);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) {
+    k_bsync<<<(uint32_t)cus * 4, 256, 0, s>>>(a);
     e = hipGetLastError();
   }
   mark(ev, 1, s);

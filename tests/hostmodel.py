@@ -249,3 +249,52 @@ def windowed(model, w: bytes, starts, ends, lane: int, base: int, block: int = 4
                 if pad <= g < pad + total:
                     kinds[o0 + g], lens[o0 + g], offs[o0 + g] = stage[g] & 0xFF, ev[k + 1] - ev[k], P + ev[k]
     return kinds, lens, offs
+
+
+def spec_walk(model, w: bytes, b: int, end: int):
+    """The hybrid plan's speculative walk of [b, end): from the start row as if a token began
+    at b, restarting one byte further on after a halt.  Returns (token starts, last restart
+    or None)."""
+    T = model.T
+    st, tok, lacc, p, rst = 0, b, b, b, None
+    starts = [b]
+    while p < end:
+        x = int(T[st + (w[p] ^ ((st >> 8) & 31))])
+        if x & EMIT:
+            tok = p
+            starts.append(p)
+        st = (x & ROWMASK) >> 2
+        if not model.mono and (x & ACC):
+            lacc = p + 1
+        p += 1
+        if st == model.sink or (not model.mono and st == model.fail):
+            if not model.mono and st == model.fail and lacc > tok:
+                tok = lacc
+            else:
+                rst, tok = tok, tok + 1
+            p, lacc, st = tok, tok, 0
+            if p < end:
+                starts.append(p)
+    return starts, rst
+
+
+def spec_plan(model, w: bytes, S: int, X: int):
+    """Cuts of the hybrid plan for a document of a refused set: lane k walks [k S, (k+1) S + X)
+    speculatively; cut k is the first position in [k S, k S + X) that starts a token in both
+    lane k-1's walk and lane k's.  None when a cut is missing or a lane restarted at or after
+    its own cut (the document then runs on one lane)."""
+    n = len(w)
+    m = -(-n // S)
+    walks = [spec_walk(model, w, k * S, min((k + 1) * S + X, n)) for k in range(m)]
+    cuts = [0]
+    for k in range(1, m):
+        common = sorted(set(t for t in walks[k - 1][0] if k * S <= t < k * S + X) &
+                        set(t for t in walks[k][0] if t < k * S + X))
+        if not common:
+            return None
+        cuts.append(common[0])
+    for k in range(m):
+        rst = walks[k][1]
+        if rst is not None and rst >= cuts[k]:
+            return None
+    return cuts

@@ -160,3 +160,40 @@ def test_batch_graph_replays(setup):
         np.testing.assert_array_equal(lens[: eager.ntokens].cpu().numpy(), want_l, err_msg=f"replay {rep}")
         np.testing.assert_array_equal(res[: nd * 32].cpu().numpy().view(P.DOC_RESULT_DTYPE), eager.docs)
         _ = batch.run(dev, docs)  # eager work between replays
+
+
+def test_batch_refused_hybrid_plan(setup):
+    """Documents of the refused set C-like-B longer than one speculative lane (4 KiB) are
+    split by the hybrid plan: each must still equal the oracle's serial scan, split clean
+    documents report many slices, and those that must fall back (the serial scan halts; a
+    block comment longer than the sync window across a lane boundary; a serial flag) run as
+    one slice."""
+    cb = INSTANCES.index(("clike_b", 1))
+    parts, recs, off = [], [], 0
+
+    def add(b, flags=0):
+        nonlocal off
+        b = np.array(b, dtype=np.uint8, copy=True)
+        parts.append(b)
+        recs.append((off, b.size, cb, flags))
+        off += b.size
+
+    for i, n in enumerate([4097, 5000, 8192, 300000, 1500000, 3000000]):
+        add(workloads.clike(n, 900 + i, bcomment=True))
+    bad = np.array(workloads.clike(200000, 910, bcomment=True), copy=True)
+    bad[150000:150002] = ord("@")  # '@' is no token: the scan halts unless this lands in a comment or string
+    add(bad)
+    long_comment = np.concatenate([workloads.clike(3000, 911), np.frombuffer(b"\n/* " + b"x" * 2000 + b" */\n", np.uint8),
+                                   workloads.clike(60000, 912)])
+    add(long_comment)
+    add(workloads.clike(100000, 913, bcomment=True), flags=1)
+    data = np.concatenate(parts)
+    docs = np.array(recs, dtype=P.DOC_DTYPE)
+    print(f"[case] hybrid plan: {docs.size} C-like-B documents, {data.size} B", flush=True)
+    _, _, batch = setup
+    r = batch.run(torch.from_numpy(data).cuda(), docs, offsets=True)
+    check_batch(setup, data, docs, r)
+    ns = r.docs["nslices"]
+    assert all(ns[i] > 1 for i in range(1, 6)), ns  # clean and longer than one lane: split
+    assert ns[7] == 1 and ns[8] == 1, ns            # the long comment and the serial flag: one slice
+    assert ns[5] >= 3000000 // 4096 // 2

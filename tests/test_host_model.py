@@ -97,3 +97,44 @@ def test_windowed_emit_model():
         if oc.lex(bad, discard=bool(mode))[2] < len(bad):
             cuts = hostmodel.plan_cuts(bad, cert, 256)
             assert hostmodel.windowed(m, bad, cuts[:-1], cuts[1:], 256, 0) is None
+
+
+def test_hybrid_plan_model():
+    """The hybrid plan for refused token sets (speculative lanes with a common-token-start
+    sync), restated on the host: whenever it cuts, every cut is a token start of the serial
+    scan and the slices lexed from their cuts concatenate to the serial scan; it falls back
+    (no cuts) on inputs whose serial scan halts and when a block comment longer than the
+    sync window spans a lane boundary."""
+    defs = T.as_tuples(T.CLIKE_B)
+    lx, oc = P.Lexer.compile(defs), oracle.OracleSet(defs)
+    m = hostmodel.Model(lx, P.LEX_MODE_DISCARD)
+    assert not lx.cert(P.LEX_MODE_DISCARD)  # refused: no useful certified byte
+    split = 0
+    for seed in range(10):
+        w = bytes(workloads.clike([30000, 70000][seed % 2], 700 + seed, bcomment=True))
+        if seed % 5 == 4:  # a stray byte; the draw may land where 0x01 is legal
+            w = w[:len(w) // 3] + b"\x01" + w[len(w) // 3:]
+        ke, le, oe, con = oc.lex(w, discard=False, offsets=True)
+        cuts = hostmodel.spec_plan(m, w, 4096, 512)
+        if cuts is None:
+            continue
+        split += 1
+        assert con == len(w), seed  # a plan that cuts never covers a halting scan
+        assert set(cuts) <= set(oe.tolist()) | {0}, seed
+        kd, ld, od, _ = oc.lex(w, discard=True, offsets=True)
+        got = []
+        for a, b in zip(cuts, cuts[1:] + [len(w)]):
+            k, l, o, c = oc.lex(w[a:b], discard=True, offsets=True)
+            assert c == b - a
+            got += list(zip(k.tolist(), l.tolist(), (o + a).tolist()))
+        assert got == list(zip(kd.tolist(), ld.tolist(), od.tolist())), seed
+    assert split >= 8
+    # malformed: the serial scan halts, so the plan falls back
+    w = bytearray(workloads.clike(30000, 9, bcomment=True))
+    w[12000:12002] = b"@@"
+    if oc.lex(bytes(w), discard=True)[2] < len(w):
+        assert hostmodel.spec_plan(m, bytes(w), 4096, 512) is None
+    # a block comment of 2000 bytes across the boundary at 4096: no common start in 512 bytes
+    w = bytes(workloads.clike(3000, 10)) + b"\n/* " + b"x" * 2000 + b" */\n" + bytes(workloads.clike(6000, 11))
+    assert oc.lex(w, discard=True)[2] == len(w)
+    assert hostmodel.spec_plan(m, w, 4096, 512) is None
