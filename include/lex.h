@@ -155,13 +155,16 @@ typedef struct {
 
 /* The configuration lex_run would use for n bytes in this mode under opts (NULL =
  * defaults): for tools and benchmarks that attribute time and bytes to kernels.  path is
- * 1, 2 or 3 as in lex_run_opts (never 0); windowed: the windowed emit applies.  Returns
- * what lex_run would return for these arguments (LEX_EINVAL, LEX_ELIMIT) or LEX_OK. */
+ * 1, 2 or 3 as in lex_run_opts (never 0); windowed: the windowed emit applies; hybrid: the
+ * hybrid plan splits a refused set (path is then 1: its count walk, scan and emit run on
+ * the speculative cuts, lane_bytes is the speculative lane).  Returns what lex_run would
+ * return for these arguments (LEX_EINVAL, LEX_ELIMIT) or LEX_OK. */
 typedef struct {
   uint32_t lane_bytes;
   uint32_t block_threads;
   int32_t path;
   int32_t windowed;
+  int32_t hybrid;
 } lex_plan_info;
 int lex_plan(const lex_dfa *dfa, uint64_t n, int mode, const lex_run_opts *opts, lex_plan_info *out);
 

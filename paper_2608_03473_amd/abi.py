@@ -40,7 +40,7 @@ LEX_EMIT_DEFAULT, LEX_EMIT_LANE = 0, 1
 
 class PlanInfo(C.Structure):
     _fields_ = [("lane_bytes", C.c_uint32), ("block_threads", C.c_uint32), ("path", C.c_int32),
-                ("windowed", C.c_int32)]
+                ("windowed", C.c_int32), ("hybrid", C.c_int32)]
 
 
 class RunOpts(C.Structure):

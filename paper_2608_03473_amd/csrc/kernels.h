@@ -60,14 +60,19 @@ struct Plan {
   // of the decoupled look-back, and the counter that hands the workgroups out in order.
   uint64_t *chunk_st;      // nblocks
   uint32_t *chunk_ctr;
+  // Hybrid plan (a refused set split speculatively; lane_bytes is the speculative lane):
+  // per lane its cut, last restart and head/tail token starts, and the fall-back flag.
+  int hybrid;
+  uint32_t *spec_cut, *spec_rst, *spec_bits, *spec_fail;
 };
+constexpr uint32_t kHybridLane = 4096;  // speculative lane bytes (at least)
 
 constexpr uint32_t kWin = 64;  // window of the windowed emit
 // Windows of n bytes at any alignment of the input, plus one.
 uint32_t windows_max(uint32_t n);
 uint32_t ck_slots(uint32_t lane_bytes);
 
-size_t workspace_bytes(uint32_t n, uint32_t lane_bytes, uint32_t block, int pipeline, int windowed);
+size_t workspace_bytes(uint32_t n, uint32_t lane_bytes, uint32_t block, int pipeline, int windowed, int hybrid);
 // Dynamic LDS of a walk workgroup: the table, its row info and, for the emit walk, a
 // 96-byte token ring per lane.
 size_t walk_lds_bytes(int nrows, uint32_t block, bool emit);
@@ -78,7 +83,7 @@ size_t window_lds_bytes(int nrows);
 size_t onepass_lds_bytes(int nrows);
 constexpr uint32_t kChunkLanes = 256;  // lanes per one-pass workgroup
 bool carve(void *ws, size_t ws_bytes, uint32_t n, uint32_t lane_bytes, uint32_t block, int pipeline,
-           int windowed, Plan &p);
+           int windowed, int hybrid, Plan &p);
 
 struct ResultDev {  // mirrors lex_result
   uint64_t ntokens;
@@ -103,6 +108,10 @@ hipError_t run_fused(const DevTable &t, const CertMap &cm, const uint8_t *cert_l
                      const Plan &p, bool serial, uint8_t *kinds, uint32_t *lens, uint64_t *offs, uint64_t cap,
                      ResultDev *res, hipStream_t s, hipEvent_t const *ev);
 
+// Hybrid plan for a refused set: speculative walks and their cuts, then the pipeline's count
+// walk, scan and emit over those cuts.
+hipError_t run_hybrid(const DevTable &t, const CertMap &cm, const uint8_t *in, const Plan &p, uint8_t *kinds,
+                      uint32_t *lens, uint64_t *offs, uint64_t cap, ResultDev *res, hipStream_t s, hipEvent_t const *ev);
 // One pass (windowed scans, block == kChunkLanes): plan, count walk, look-back and windowed
 // emit in one launch, then the scan and the lane emit's fallback.
 hipError_t run_onepass(const DevTable &t, const CertMap &cm, const uint8_t *cert_lut, const uint8_t *in,

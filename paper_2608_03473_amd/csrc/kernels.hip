@@ -1664,7 +1664,7 @@ __global__ void k_onepass_reset(uint64_t *st, uint32_t n, uint32_t *ctr) {
 // start within kSpecX bytes, or when a lane restarted at or after its own cut (the serial
 // scan halts there: the one-lane scan then reports the error as usual).
 constexpr int kMaxInst = 8;
-constexpr uint32_t kSpecLane = 4096;
+constexpr uint32_t kSpecLane = kHybridLane;
 constexpr uint32_t kSpecX = 512;
 constexpr uint32_t kSpecWords = kSpecX / 32;
 
@@ -2181,6 +2181,62 @@ __global__ void __launch_bounds__(256) k_bemit(BatchArgs a) {
   }
 }
 
+// ------------------------------------------------- hybrid plan for a single buffer
+// The hybrid plan (see the batch notes above) for one buffer of a refused set: lane k walks
+// [k S, (k+1) S + kSpecX) speculatively (k_hspec), k_hsync finds the cuts, and k_hcuts
+// writes them as the planned lane boundaries, or {0, n, ..., n} (one slice) when the plan
+// falls back.  The count walk, scan and emit of the pipeline path then run unchanged.
+struct HybridArgs {
+  const uint8_t *in;
+  uint32_t n, nlanes, S;
+  uint32_t *cut, *rst, *bits, *fail;  // per lane: cut, last restart, head then tail; one flag
+  uint32_t *cuts;                     // nlanes + 1 lane boundaries
+};
+
+__global__ void __launch_bounds__(256) k_hspec(WalkArgs a, HybridArgs h) {
+  const Lds l = carve_lds(a.nrows);
+  stage_tables(a, l, false);
+  const Tables tb{lds_bytes_of(l.T), l.info, l.kind, a.sink, a.fail, 0};
+  const uint32_t gid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid == 0) *h.fail = 0;
+  for (uint32_t k = gid; k < h.nlanes; k += gridDim.x * blockDim.x) {
+    const uint32_t b = k * h.S;
+    const uint32_t b2 = (uint32_t)min<uint64_t>((uint64_t)(k + 1) * h.S, h.n);
+    const uint32_t end = (uint32_t)min<uint64_t>((uint64_t)b2 + kSpecX, h.n);
+    uint32_t *bits = h.bits + (size_t)k * 2 * kSpecWords;
+    uint32_t rst;
+    if (a.fail == a.sink) walk_spec<true>(tb, h.in, h.n, b, end, b2, bits, bits + kSpecWords, rst);
+    else walk_spec<false>(tb, h.in, h.n, b, end, b2, bits, bits + kSpecWords, rst);
+    h.rst[k] = rst;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_hsync(HybridArgs h) {
+  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < h.nlanes; k += gridDim.x * blockDim.x) {
+    uint32_t cut = 0;
+    bool ok = true;
+    if (k) {
+      const uint32_t *head = h.bits + (size_t)k * 2 * kSpecWords;
+      const uint32_t *tail = h.bits + (size_t)(k - 1) * 2 * kSpecWords + kSpecWords;
+      cut = kNone;
+      for (uint32_t w = 0; w < kSpecWords && cut == kNone; ++w) {
+        const uint32_t x = head[w] & tail[w];
+        if (x) cut = k * h.S + 32 * w + (__ffs(x) - 1);
+      }
+      ok = cut != kNone;
+    }
+    if (ok && h.rst[k] != kNone && h.rst[k] >= cut) ok = false;
+    h.cut[k] = cut;
+    if (!ok) *h.fail = 1;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_hcuts(HybridArgs h) {
+  const bool fail = *h.fail != 0;
+  for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k <= h.nlanes; k += gridDim.x * blockDim.x)
+    h.cuts[k] = k == h.nlanes ? h.n : fail ? (k ? h.n : 0) : h.cut[k];
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ host side
@@ -2189,7 +2245,7 @@ uint32_t windows_max(uint32_t n) { return (uint32_t)(((uint64_t)n + 2 * kWin - 1
 // of their lane's end).
 uint32_t ck_slots(uint32_t lane_bytes) { return lane_bytes / kWin + 4; }
 
-static size_t carve_layout(uint32_t n, uint32_t lane_bytes, uint32_t block, int pipeline, int windowed,
+static size_t carve_layout(uint32_t n, uint32_t lane_bytes, uint32_t block, int pipeline, int windowed, int hybrid,
                            size_t *offs) {
   const uint32_t nlanes = n ? (n + lane_bytes - 1) / lane_bytes : 1;
   const uint32_t nblocks = (nlanes + block - 1) / block;
@@ -2231,18 +2287,20 @@ static size_t carve_layout(uint32_t n, uint32_t lane_bytes, uint32_t block, int 
   if (windowed) at += align256((size_t)nblocks * 8);
   offs[16] = at;  // one pass: workgroup counter
   if (windowed) at += align256(4);
+  offs[17] = at;  // hybrid plan: per lane cut, last restart, head and tail token starts; a flag
+  if (hybrid) at += 2 * align256((size_t)nlanes * 4) + align256((size_t)nlanes * 2 * kSpecWords * 4) + align256(4);
   return at;
 }
 
-size_t workspace_bytes(uint32_t n, uint32_t lane_bytes, uint32_t block, int pipeline, int windowed) {
-  size_t offs[17];
-  return carve_layout(n, lane_bytes, block, pipeline, windowed, offs);
+size_t workspace_bytes(uint32_t n, uint32_t lane_bytes, uint32_t block, int pipeline, int windowed, int hybrid) {
+  size_t offs[18];
+  return carve_layout(n, lane_bytes, block, pipeline, windowed, hybrid, offs);
 }
 
 bool carve(void *ws, size_t ws_bytes, uint32_t n, uint32_t lane_bytes, uint32_t block, int pipeline, int windowed,
-           Plan &p) {
-  size_t offs[17];
-  const size_t need = carve_layout(n, lane_bytes, block, pipeline, windowed, offs);
+           int hybrid, Plan &p) {
+  size_t offs[18];
+  const size_t need = carve_layout(n, lane_bytes, block, pipeline, windowed, hybrid, offs);
   if (ws_bytes < need || !ws) return false;
   uint8_t *b = static_cast<uint8_t *>(ws);
   p.n = n;
@@ -2271,6 +2329,16 @@ bool carve(void *ws, size_t ws_bytes, uint32_t n, uint32_t lane_bytes, uint32_t 
   p.blk_lnz = reinterpret_cast<int32_t *>(b + offs[14]);
   p.chunk_st = windowed ? reinterpret_cast<uint64_t *>(b + offs[15]) : nullptr;
   p.chunk_ctr = windowed ? reinterpret_cast<uint32_t *>(b + offs[16]) : nullptr;
+  p.hybrid = hybrid;
+  if (hybrid) {
+    uint8_t *h = b + offs[17];
+    p.spec_cut = reinterpret_cast<uint32_t *>(h), h += align256((size_t)p.nlanes * 4);
+    p.spec_rst = reinterpret_cast<uint32_t *>(h), h += align256((size_t)p.nlanes * 4);
+    p.spec_bits = reinterpret_cast<uint32_t *>(h), h += align256((size_t)p.nlanes * 2 * kSpecWords * 4);
+    p.spec_fail = reinterpret_cast<uint32_t *>(h);
+  } else {
+    p.spec_cut = p.spec_rst = p.spec_bits = p.spec_fail = nullptr;
+  }
   return true;
 }
 
@@ -2558,6 +2626,27 @@ hipError_t run_fused(const DevTable &t, const CertMap &cm, const uint8_t *cert_l
   if (one && p.nlanes != 1) return hipErrorInvalidValue;
   const WalkArgs a = walk_args(t, cm, in, p, kinds, lens, offs, cap, res, cert_lut);
   return count_scan_emit<true>(t, a, p, cap, res, s, ev);
+}
+
+hipError_t run_hybrid(const DevTable &t, const CertMap &cm, const uint8_t *in, const Plan &p, uint8_t *kinds,
+                      uint32_t *lens, uint64_t *offs, uint64_t cap, ResultDev *res, hipStream_t s, hipEvent_t const *ev) {
+  if (!p.hybrid || !p.spec_cut || p.nlanes < 2 || p.lane_bytes < kSpecX) return hipErrorInvalidValue;
+  WalkArgs a = walk_args(t, cm, in, p, kinds, lens, offs, cap, res, nullptr);
+  HybridArgs h{in, p.n, p.nlanes, p.lane_bytes, p.spec_cut, p.spec_rst, p.spec_bits, p.spec_fail, p.cuts};
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  const uint32_t g = std::max<uint32_t>(1, std::min<uint32_t>((p.nlanes + 255) / 256, (uint32_t)cus * 4));
+  mark(ev, 0, s);
+  k_hspec<<<g, 256, lds_bytes(t.nrows, 256, false), s>>>(a, h);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_hsync<<<g, 256, 0, s>>>(h);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_hcuts<<<std::max<uint32_t>(1, std::min<uint32_t>((p.nlanes + 256) / 256, (uint32_t)cus * 4)), 256, 0, s>>>(h);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return count_scan_emit<false>(t, a, p, cap, res, s, ev);
 }
 
 hipError_t run_onepass(const DevTable &t, const CertMap &cm, const uint8_t *cert_lut, const uint8_t *in,

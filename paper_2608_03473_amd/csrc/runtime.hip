@@ -149,6 +149,7 @@ struct Resolved {
   int table;  // 0 exact, 1 discard
   bool windowed;
   bool onepass;  // fused, in one pass
+  bool hybrid;   // a refused set split speculatively (pipeline's count, scan and emit)
 };
 
 uint32_t default_lane_bytes(uint64_t n, bool onepass) {
@@ -171,7 +172,12 @@ uint32_t default_block(int nrows) {
 int resolve(const lex_dfa *d, uint64_t n, int mode, const lex_run_opts *o, Resolved &r) {
   if (mode < 0 || mode > 3) return LEX_EINVAL;
   r.table = mode & 1;
-  r.serial = (mode & 2) != 0 || d->cm[r.table].nbytes == 0;
+  // A refused set (no useful certified byte) is split by the hybrid plan when the buffer is
+  // longer than one speculative lane and the mode does not ask for a serial scan.
+  const bool refused = d->cm[r.table].nbytes == 0;
+  const uint32_t spec = std::max<uint32_t>(lexk::kHybridLane, o && o->lane_bytes ? o->lane_bytes : 0);
+  r.hybrid = refused && !(mode & 2) && n > spec;
+  r.serial = (mode & 2) != 0 || (refused && !r.hybrid);
   const int asked = o && o->path ? o->path : 0;
   if (asked < 0 || asked > 3) return LEX_EINVAL;
   const int32_t bt = o ? o->block_threads : 0;
@@ -186,6 +192,15 @@ int resolve(const lex_dfa *d, uint64_t n, int mode, const lex_run_opts *o, Resol
               lexk::onepass_lds_bytes(d->c.nrows) <= 160 * 1024;
   r.path = asked == 1 ? 1 : 2;
   r.block = r.onepass ? lexk::kChunkLanes : bt ? (uint32_t)bt : default_block(d->c.nrows);
+  if (r.hybrid) {  // speculative lanes and cuts, then the pipeline's count, scan and emit
+    r.onepass = false;
+    r.path = 1;
+    if (r.block != 256u && r.block != 512u && r.block != 1024u) return LEX_EINVAL;
+    if (lexk::walk_lds_bytes(d->c.nrows, r.block, true) > 160 * 1024) return LEX_ELIMIT;
+    if (o && o->lane_bytes && (o->lane_bytes < 16 || (o->lane_bytes & 15))) return LEX_EINVAL;
+    r.lane_bytes = spec;
+    return LEX_OK;
+  }
   if (r.block != 256u && r.block != 512u && r.block != 1024u) return LEX_EINVAL;
   if (lexk::walk_lds_bytes(d->c.nrows, r.block, true) > 160 * 1024) return LEX_ELIMIT;
   uint32_t lb = o && o->lane_bytes ? o->lane_bytes : default_lane_bytes(n, r.onepass);
@@ -295,7 +310,7 @@ int lex_tables(const lex_dfa *d, int mode, uint32_t *table, size_t table_entries
 size_t lex_workspace_size(const lex_dfa *d, uint64_t n, int mode, const lex_run_opts *opts) {
   Resolved r;
   if (!d || n > 0xFFFFFFF0ull || resolve(d, n, mode, opts, r) != LEX_OK) return 0;
-  return lexk::workspace_bytes((uint32_t)n, r.lane_bytes, r.block, r.path == 1, r.windowed);
+  return lexk::workspace_bytes((uint32_t)n, r.lane_bytes, r.block, r.path == 1 && !r.hybrid, r.windowed, r.hybrid);
 }
 
 int lex_plan(const lex_dfa *d, uint64_t n, int mode, const lex_run_opts *opts, lex_plan_info *out) {
@@ -308,6 +323,7 @@ int lex_plan(const lex_dfa *d, uint64_t n, int mode, const lex_run_opts *opts, l
   out->block_threads = r.block;
   out->path = r.onepass ? 3 : r.path;
   out->windowed = r.windowed ? 1 : 0;
+  out->hybrid = r.hybrid ? 1 : 0;
   return LEX_OK;
 }
 
@@ -323,7 +339,8 @@ int lex_run(const lex_dfa *d, const uint8_t *d_bytes, uint64_t n, int mode, uint
   int rc = resolve(d, n, mode, opts, r);
   if (rc != LEX_OK) return rc;
   lexk::Plan p;
-  if (!lexk::carve(d_ws, ws_bytes, (uint32_t)n, r.lane_bytes, r.block, r.path == 1, r.windowed, p))
+  if (!lexk::carve(d_ws, ws_bytes, (uint32_t)n, r.lane_bytes, r.block, r.path == 1 && !r.hybrid, r.windowed, r.hybrid,
+                   p))
     return LEX_ELIMIT;
   const int m = r.table;
   DevCopy *dc = device_copy(const_cast<lex_dfa *>(d));
@@ -333,7 +350,8 @@ int lex_run(const lex_dfa *d, const uint8_t *d_bytes, uint64_t n, int mode, uint
   hipStream_t s = static_cast<hipStream_t>(stream);
   auto *res = reinterpret_cast<lexk::ResultDev *>(d_result);
   hipEvent_t const *ev = opts && opts->events ? reinterpret_cast<hipEvent_t const *>(opts->events) : nullptr;
-  hipError_t e = r.path == 1   ? lexk::run_pipeline(t, d->cm[m], d_bytes, p, r.serial, d_kinds, d_lens, d_offsets,
+  hipError_t e = r.hybrid      ? lexk::run_hybrid(t, d->cm[m], d_bytes, p, d_kinds, d_lens, d_offsets, cap, res, s, ev)
+                 : r.path == 1 ? lexk::run_pipeline(t, d->cm[m], d_bytes, p, r.serial, d_kinds, d_lens, d_offsets,
                                                     cap, res, s, ev)
                  : r.onepass ? lexk::run_onepass(t, d->cm[m], dc->d_cert_lut[m], d_bytes, p, r.serial, d_kinds,
                                                  d_lens, d_offsets, cap, res, s, ev)

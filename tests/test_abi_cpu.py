@@ -57,7 +57,13 @@ def test_plan_query():
     cl = P.Lexer.compile(T.as_tuples(T.CLIKE_L))
     js = P.Lexer.compile(T.as_tuples(T.JSON))
     d = cl.plan(512 << 20)
-    assert d == {"lane_bytes": 2048, "block_threads": 256, "path": 3, "windowed": 1}
+    assert d == {"lane_bytes": 2048, "block_threads": 256, "path": 3, "windowed": 1, "hybrid": 0}
+    cb = P.Lexer.compile(T.as_tuples(T.CLIKE_B))  # refused: the hybrid plan above one speculative lane
+    h = cb.plan(1 << 20, P.LEX_MODE_DISCARD)
+    assert h["hybrid"] == 1 and h["path"] == 1 and h["lane_bytes"] == 4096
+    assert cb.plan(1 << 20, P.LEX_MODE_DISCARD, P.RunOpts(lane_bytes=8192))["lane_bytes"] == 8192
+    assert cb.plan(4096, P.LEX_MODE_DISCARD)["hybrid"] == 0
+    assert cb.plan(1 << 20, P.LEX_MODE_DISCARD | P.LEX_MODE_SERIAL)["hybrid"] == 0
     assert cl.plan(512 << 20, opts=P.RunOpts(path=2))["lane_bytes"] == 1024
     assert cl.plan(512 << 20, opts=P.RunOpts(path=2))["path"] == 2
     assert cl.plan(512 << 20, opts=P.RunOpts(path=1))["path"] == 1

@@ -224,10 +224,25 @@ def test_json_discard(path):
 
 
 def test_clike_b_refused():
+    """C-like-B has no useful certified byte.  Buffers longer than one speculative lane are
+    split by the hybrid plan (and must still equal the serial scan); it falls back to one
+    slice when the serial scan halts or a block comment longer than the sync window spans a
+    lane boundary; serial mode and short buffers are one slice."""
     cb = workloads.clike(400000, 9, bcomment=True)
     r = check("clike_b", cb, P.LEX_MODE_DISCARD)
+    assert r.nslices > 50
+    r = check("clike_b", cb, P.LEX_MODE_DISCARD | P.LEX_MODE_SERIAL)
     assert r.nslices == 1
     check("clike_b", np.frombuffer(b"/* a\nb */ x /* y", np.uint8), P.LEX_MODE_DISCARD)
+    bad = np.array(cb[:100000], copy=True)
+    bad[70000:70002] = ord("@")
+    check("clike_b", bad, P.LEX_MODE_DISCARD, label="halting")
+    long_comment = np.concatenate([workloads.clike(3000, 11), np.frombuffer(b"\n/* " + b"x" * 2000 + b" */\n", np.uint8),
+                                   workloads.clike(60000, 12)])
+    r = check("clike_b", long_comment, P.LEX_MODE_DISCARD, label="long comment across a lane boundary")
+    assert r.nslices == 1
+    for n in (4097, 4096 + 600, 9000):
+        check("clike_b", cb[:n], P.LEX_MODE_DISCARD, pad_front=3, label="just over one lane")
 
 
 def test_log_planning_workload():
