@@ -1660,9 +1660,12 @@ __global__ void k_onepass_reset(uint64_t *st, uint32_t n, uint32_t *ctr) {
 // both start a token is a token start of the serial scan, and from there both walks agree
 // (both restart in the start row on the same bytes).  By induction the cuts found this
 // way are serial token boundaries, and the slices between them are counted and emitted
-// like certified slices.  A document falls back to one lane when a boundary finds no common
-// start within kSpecX bytes, or when a lane restarted at or after its own cut (the serial
-// scan halts there: the one-lane scan then reports the error as usual).
+// like certified slices.  The last lane's window reaches the document's end; when it finds
+// no common start (a token runs from before its start to the end), lane k - 1, which is the
+// serial scan up to the end, takes the rest.  A document falls back to one lane when another
+// boundary finds no common start within kSpecX bytes, or when a lane restarted at or after
+// its own cut (the serial scan halts there: the one-lane scan then reports the error as
+// usual).
 constexpr int kMaxInst = 8;
 constexpr uint32_t kSpecLane = kHybridLane;
 constexpr uint32_t kSpecX = 512;
@@ -1958,6 +1961,9 @@ __global__ void __launch_bounds__(256) k_bsync(BatchArgs a) {
         const uint32_t x = head[w] & tail[w];
         if (x) cut = k * a.spec_bytes + 32 * w + (__ffs(x) - 1);
       }
+      // the last lane's window reaches the end: with no common token start, lane k - 1
+      // (the serial scan up to the end) takes the rest
+      if (cut == kNone && k + 1 == a.lanes_of[d]) cut = a.docs[d].length;
       ok = cut != kNone;
     }
     const uint32_t rst = a.spec_rst[i];
@@ -2223,6 +2229,7 @@ __global__ void __launch_bounds__(256) k_hsync(HybridArgs h) {
         const uint32_t x = head[w] & tail[w];
         if (x) cut = k * h.S + 32 * w + (__ffs(x) - 1);
       }
+      if (cut == kNone && k + 1 == h.nlanes) cut = h.n;  // as in k_bsync
       ok = cut != kNone;
     }
     if (ok && h.rst[k] != kNone && h.rst[k] >= cut) ok = false;

@@ -281,8 +281,9 @@ def spec_walk(model, w: bytes, b: int, end: int):
 def spec_plan(model, w: bytes, S: int, X: int):
     """Cuts of the hybrid plan for a document of a refused set: lane k walks [k S, (k+1) S + X)
     speculatively; cut k is the first position in [k S, k S + X) that starts a token in both
-    lane k-1's walk and lane k's.  None when a cut is missing or a lane restarted at or after
-    its own cut (the document then runs on one lane)."""
+    lane k-1's walk and lane k's (for the last lane, whose window reaches the end, the end when
+    there is none: lane k-1's walk is then the serial scan up to the end).  None when a cut is
+    missing or a lane restarted at or after its own cut (the document then runs on one lane)."""
     n = len(w)
     m = -(-n // S)
     walks = [spec_walk(model, w, k * S, min((k + 1) * S + X, n)) for k in range(m)]
@@ -290,6 +291,8 @@ def spec_plan(model, w: bytes, S: int, X: int):
     for k in range(1, m):
         common = sorted(set(t for t in walks[k - 1][0] if k * S <= t < k * S + X) &
                         set(t for t in walks[k][0] if t < k * S + X))
+        if not common and k == m - 1:
+            common = [n]  # lane k - 1's walk reached the end: it takes the rest
         if not common:
             return None
         cuts.append(common[0])

@@ -187,6 +187,8 @@ def test_batch_refused_hybrid_plan(setup):
                                    workloads.clike(60000, 912)])
     add(long_comment)
     add(workloads.clike(100000, 913, bcomment=True), flags=1)
+    # the last token (padding LFs: one whitespace token) spans the last lane's start
+    add(np.concatenate([workloads.clike(8100, 914, bcomment=True), np.full(300, 10, np.uint8)]))
     data = np.concatenate(parts)
     docs = np.array(recs, dtype=P.DOC_DTYPE)
     print(f"[case] hybrid plan: {docs.size} C-like-B documents, {data.size} B", flush=True)
@@ -196,4 +198,5 @@ def test_batch_refused_hybrid_plan(setup):
     ns = r.docs["nslices"]
     assert all(ns[i] > 1 for i in range(1, 6)), ns  # clean and longer than one lane: split
     assert ns[7] == 1 and ns[8] == 1, ns            # the long comment and the serial flag: one slice
+    assert ns[9] == 2, ns                            # the last lane empty: the previous one takes the rest
     assert ns[5] >= 3000000 // 4096 // 2

@@ -243,6 +243,9 @@ def test_clike_b_refused():
     assert r.nslices == 1
     for n in (4097, 4096 + 600, 9000):
         check("clike_b", cb[:n], P.LEX_MODE_DISCARD, pad_front=3, label="just over one lane")
+    tail = np.concatenate([workloads.clike(8100, 13, bcomment=True), np.full(300, 10, np.uint8)])
+    r = check("clike_b", tail, P.LEX_MODE_DISCARD, label="last token across the last lane's start")
+    assert r.nslices == 2
 
 
 def test_log_planning_workload():

@@ -134,6 +134,17 @@ def test_hybrid_plan_model():
     w[12000:12002] = b"@@"
     if oc.lex(bytes(w), discard=True)[2] < len(w):
         assert hostmodel.spec_plan(m, bytes(w), 4096, 512) is None
+    # the last token (a run of padding LFs, one whitespace token) spans the last lane's start:
+    # the previous lane takes the rest and the plan still cuts
+    w = bytes(workloads.clike(8100, 12, bcomment=True)) + b"\n" * 300
+    cuts = hostmodel.spec_plan(m, w, 4096, 512)
+    assert cuts is not None and cuts[-1] == len(w)
+    kd = oc.lex(w, discard=True, offsets=True)
+    got = []
+    for a, b in zip(cuts, cuts[1:] + [len(w)]):
+        k, l, o, c = oc.lex(w[a:b], discard=True, offsets=True)
+        got += list(zip(k.tolist(), l.tolist(), (o + a).tolist()))
+    assert got == list(zip(kd[0].tolist(), kd[1].tolist(), kd[2].tolist()))
     # a block comment of 2000 bytes across the boundary at 4096: no common start in 512 bytes
     w = bytes(workloads.clike(3000, 10)) + b"\n/* " + b"x" * 2000 + b" */\n" + bytes(workloads.clike(6000, 11))
     assert oc.lex(w, discard=True)[2] == len(w)
