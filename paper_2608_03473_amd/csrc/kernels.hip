@@ -1668,7 +1668,7 @@ __global__ void k_onepass_reset(uint64_t *st, uint32_t n, uint32_t *ctr) {
 // usual).
 constexpr int kMaxInst = 8;
 constexpr uint32_t kSpecLane = kHybridLane;
-constexpr uint32_t kSpecX = 512;
+constexpr uint32_t kSpecX = 2048;  // at most kSpecLane
 constexpr uint32_t kSpecWords = kSpecX / 32;
 
 struct BatchInst {

@@ -183,7 +183,7 @@ def test_batch_refused_hybrid_plan(setup):
     bad = np.array(workloads.clike(200000, 910, bcomment=True), copy=True)
     bad[150000:150002] = ord("@")  # '@' is no token: the scan halts unless this lands in a comment or string
     add(bad)
-    long_comment = np.concatenate([workloads.clike(3000, 911), np.frombuffer(b"\n/* " + b"x" * 2000 + b" */\n", np.uint8),
+    long_comment = np.concatenate([workloads.clike(3000, 911), np.frombuffer(b"\n/* " + b"x" * 5000 + b" */\n", np.uint8),
                                    workloads.clike(60000, 912)])
     add(long_comment)
     add(workloads.clike(100000, 913, bcomment=True), flags=1)

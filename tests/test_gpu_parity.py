@@ -237,7 +237,7 @@ def test_clike_b_refused():
     bad = np.array(cb[:100000], copy=True)
     bad[70000:70002] = ord("@")
     check("clike_b", bad, P.LEX_MODE_DISCARD, label="halting")
-    long_comment = np.concatenate([workloads.clike(3000, 11), np.frombuffer(b"\n/* " + b"x" * 2000 + b" */\n", np.uint8),
+    long_comment = np.concatenate([workloads.clike(3000, 11), np.frombuffer(b"\n/* " + b"x" * 5000 + b" */\n", np.uint8),
                                    workloads.clike(60000, 12)])
     r = check("clike_b", long_comment, P.LEX_MODE_DISCARD, label="long comment across a lane boundary")
     assert r.nslices == 1

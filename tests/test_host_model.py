@@ -104,7 +104,7 @@ def test_hybrid_plan_model():
     sync), restated on the host: whenever it cuts, every cut is a token start of the serial
     scan and the slices lexed from their cuts concatenate to the serial scan; it falls back
     (no cuts) on inputs whose serial scan halts and when a block comment longer than the
-    sync window spans a lane boundary."""
+    sync window (2 KiB) spans a lane boundary."""
     defs = T.as_tuples(T.CLIKE_B)
     lx, oc = P.Lexer.compile(defs), oracle.OracleSet(defs)
     m = hostmodel.Model(lx, P.LEX_MODE_DISCARD)
@@ -115,7 +115,7 @@ def test_hybrid_plan_model():
         if seed % 5 == 4:  # a stray byte; the draw may land where 0x01 is legal
             w = w[:len(w) // 3] + b"\x01" + w[len(w) // 3:]
         ke, le, oe, con = oc.lex(w, discard=False, offsets=True)
-        cuts = hostmodel.spec_plan(m, w, 4096, 512)
+        cuts = hostmodel.spec_plan(m, w, 4096, 2048)
         if cuts is None:
             continue
         split += 1
@@ -133,11 +133,11 @@ def test_hybrid_plan_model():
     w = bytearray(workloads.clike(30000, 9, bcomment=True))
     w[12000:12002] = b"@@"
     if oc.lex(bytes(w), discard=True)[2] < len(w):
-        assert hostmodel.spec_plan(m, bytes(w), 4096, 512) is None
+        assert hostmodel.spec_plan(m, bytes(w), 4096, 2048) is None
     # the last token (a run of padding LFs, one whitespace token) spans the last lane's start:
     # the previous lane takes the rest and the plan still cuts
     w = bytes(workloads.clike(8100, 12, bcomment=True)) + b"\n" * 300
-    cuts = hostmodel.spec_plan(m, w, 4096, 512)
+    cuts = hostmodel.spec_plan(m, w, 4096, 2048)
     assert cuts is not None and cuts[-1] == len(w)
     kd = oc.lex(w, discard=True, offsets=True)
     got = []
@@ -145,7 +145,7 @@ def test_hybrid_plan_model():
         k, l, o, c = oc.lex(w[a:b], discard=True, offsets=True)
         got += list(zip(k.tolist(), l.tolist(), (o + a).tolist()))
     assert got == list(zip(kd[0].tolist(), kd[1].tolist(), kd[2].tolist()))
-    # a block comment of 2000 bytes across the boundary at 4096: no common start in 512 bytes
-    w = bytes(workloads.clike(3000, 10)) + b"\n/* " + b"x" * 2000 + b" */\n" + bytes(workloads.clike(6000, 11))
+    # a block comment of 5000 bytes across the boundary at 4096: no common start in 2048 bytes
+    w = bytes(workloads.clike(3000, 10)) + b"\n/* " + b"x" * 5000 + b" */\n" + bytes(workloads.clike(6000, 11))
     assert oc.lex(w, discard=True)[2] == len(w)
-    assert hostmodel.spec_plan(m, w, 4096, 512) is None
+    assert hostmodel.spec_plan(m, w, 4096, 2048) is None
