@@ -40,6 +40,7 @@ def parse():
     ap.add_argument("--batch-docs", type=int, default=50000)
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-framed", action="store_true", help="skip the framed-document leg")
     ap.add_argument("--serve-seconds", type=float, default=4.0, help="per arrival rate (plus 1 s warm-up)")
     ap.add_argument("--copy-ref", action="store_true",
                     help="also run one plain device copy of n bytes (scale for HBM counters)")
@@ -161,6 +162,9 @@ def main():
         del data, kinds, lens, ws
         torch.cuda.empty_cache()
         out["batched"] = batched_leg(args)
+    if not args.no_framed:
+        torch.cuda.empty_cache()
+        out["framed"] = framed_leg(args)
     if not args.no_serving:
         torch.cuda.empty_cache()
         out["serving"] = serving_leg(args)
@@ -285,6 +289,53 @@ def batched_leg(args):
         "same_token_counts": same,
         "refused_docs": int((sets == workloads.DOC_B).sum()), **crit,
     }
+
+
+def framed_leg(args):
+    """Framing at the producer: a --n byte C-like-B document whose records (8 lines each)
+    are opened by the reserved byte 0x1E, scanned in exact mode by the C-like-B set framed
+    by that byte (lex_compile_framed: 0x1E certified, so the certified planner splits it),
+    against the same-seed unframed document under the unframed set (refused: the hybrid
+    plan).  Inputs resident in HBM, outputs and workspace preallocated, --steps timed scans
+    after --warmup each."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from workloads import tokensets as T
+    import paper_2608_03473_amd as P
+
+    dev = torch.device("cuda", 0)
+    n, mode = args.n, P.LEX_MODE_EXACT
+    defs = T.as_tuples(T.CLIKE_B)
+    out = {"workload": f"C-like-B exact mode, {n} B C-like corpus with block comments (seed {args.seed}); "
+                       "framed: records of 8 lines opened by 0x1E"}
+    kinds = torch.empty(n, dtype=torch.uint8, device=dev)
+    lens = torch.empty(n, dtype=torch.int32, device=dev)
+    res = torch.zeros(3, dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream()
+    for key, lx, frame in (("framed", P.Lexer.compile_framed(defs), 8), ("unframed", P.Lexer.compile(defs), 0)):
+        host = workloads.clike(n, args.seed, bcomment=True, frame=frame)
+        data = torch.from_numpy(host).to(dev)
+        ws = torch.empty(lx.workspace_size(n, mode), dtype=torch.uint8, device=dev)
+        for _ in range(args.warmup):
+            lx.run_into(data, n, mode, kinds, lens, None, n, res, ws, None, stream)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            lx.run_into(data, n, mode, kinds, lens, None, n, res, ws, None, stream)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) * 1e3 / args.steps
+        r = res.cpu().numpy()
+        plan = lx.plan(n, mode)
+        out[key] = {"gbs": round(n / (ms * 1e-3) / 1e9, 3), "ms": round(ms, 3), "tokens": int(r[0]),
+                    "error_offset": int(r[1]), "slices": int((int(r[2]) >> 32) & 0xFFFFFFFF),
+                    "path": plan["path"], "hybrid": plan["hybrid"], "lane_bytes": plan["lane_bytes"]}
+        if frame:
+            out[key]["separators"] = int((host == 0x1E).sum())
+        log(args, f"framed leg {key}: {out[key]}")
+        del data, ws
+    return out
 
 
 def serving_leg(args):

@@ -97,6 +97,18 @@ typedef struct {
  * bytes, may be NULL). */
 int lex_compile(const lex_tokdef *defs, uint32_t ndefs, lex_dfa **out, char *err, size_t errlen);
 
+/* Framing at the producer (Section 7.1): compiles the ndefs (1..254) definitions with the
+ * byte `reserved` (0..255) taken out of every byte class of every pattern, so that no token
+ * of theirs contains it at any position, and appends one more definition, kind ndefs, whose
+ * only word is that byte (priority 0, discarded iff reserved_discard != 0).  The reserved
+ * byte is then consumed live only from q0 and is certified by Definition 2 whatever the
+ * set was; a producer that writes it only at token boundaries (escaping it elsewhere) gets
+ * a document that splits at every occurrence with the serial token stream reproduced.  A
+ * pattern whose language becomes empty stays valid (its kind never matches).  Ownership,
+ * device upload and errors as for lex_compile. */
+int lex_compile_framed(const lex_tokdef *defs, uint32_t ndefs, uint32_t reserved, int reserved_discard,
+                       lex_dfa **out, char *err, size_t errlen);
+
 /* Builds a lexer from a hand-built automaton (the examples of Section 4.1): next is a
  * host array of nstates*256 targets (-1 = undefined), accept[q] a token index in
  * [0, ntok) or -1, discard[t] flags t in I (ntok entries, may be NULL for I empty).  The

@@ -14,7 +14,8 @@ What it computes (see oracle.cc for the paper map):
   * ``OracleSet.lex_chunked`` -- the chunked scan of Theorems 1 and 3 with Corollary 1's
                                  truncation;
   * ``OracleSet.bruteforce``  -- the exhaustive sweep of Section 6.1 plus the lemma checks;
-  * ``cert_table``            -- certificates of a hand-built automaton (Section 4.1).
+  * ``cert_table``            -- certificates of a hand-built automaton (Section 4.1);
+  * ``OracleSet(defs, reserved=r)`` -- the set framed by a reserved byte (Section 7.1).
 """
 from __future__ import annotations
 
@@ -71,6 +72,8 @@ def _load():
     P = C.c_void_p
     lib.orc_compile.restype = P
     lib.orc_compile.argtypes = [P, C.c_uint32, C.c_char_p, C.c_size_t]
+    lib.orc_compile_framed.restype = P
+    lib.orc_compile_framed.argtypes = [P, C.c_uint32, C.c_uint32, C.c_int, C.c_char_p, C.c_size_t]
     lib.orc_free.argtypes = [P]
     lib.orc_nkinds.restype = C.c_uint32
     lib.orc_nkinds.argtypes = [P]
@@ -129,7 +132,9 @@ def _norm_defs(defs):
 class OracleSet:
     """A token set compiled by the oracle (patterns -> per-kind Thompson NFAs)."""
 
-    def __init__(self, defs):
+    def __init__(self, defs, reserved: int | None = None, reserved_discard: bool = False):
+        """reserved: frame the set by that byte (Section 7.1): it leaves every pattern and
+        becomes kind len(defs), a one-byte token of its own."""
         lib = _load()
         self.defs = _norm_defs(defs)
         arr = (_Def * len(self.defs))()
@@ -140,11 +145,16 @@ class OracleSet:
             arr[i].priority = pr
             arr[i].discard = 1 if dc else 0
         err = C.create_string_buffer(256)
-        h = lib.orc_compile(arr, len(self.defs), err, 256)
+        if reserved is None:
+            h = lib.orc_compile(arr, len(self.defs), err, 256)
+        else:
+            h = lib.orc_compile_framed(arr, len(self.defs), int(reserved), 1 if reserved_discard else 0, err, 256)
         if not h:
             raise ValueError(err.value.decode("latin-1"))
         self._h = h
         self.nkinds = lib.orc_nkinds(h)
+        if reserved is not None:
+            self.defs = self.defs + [(b"(reserved byte)", 0, bool(reserved_discard))]
         self.discard_kinds = frozenset(i for i, d in enumerate(self.defs) if d[2])
 
     def __del__(self):

@@ -19,6 +19,7 @@
 //   Theorem 2 (witness w = u b v)  -> orc_witness()
 //   Theorems 1, 3, Corollary 1     -> lex_chunked()
 //   Section 6.1 (exhaustive sweep) -> orc_bruteforce()
+//   Section 7.1 (reserved byte)    -> orc_compile_framed()
 //
 // Parity status: every function here is pinned by the CPU test-suite
 // (printed examples, closed forms, brute force, a library regex engine);
@@ -867,14 +868,17 @@ bool same(const std::vector<Tok> &a, const std::vector<Tok> &b) {
 // ================================================================ C API
 extern "C" {
 
-orc_set *orc_compile(const orc_def *defs, uint32_t ndefs, char *err, size_t errlen) {
+orc_set *orc_compile_framed(const orc_def *defs, uint32_t ndefs, uint32_t r, int r_discard, char *err,
+                            size_t errlen) {
+  // r < 256 reserves byte r; r == 256 (orc_compile) reserves nothing.
   auto seterr = [&](const std::string &m) {
     if (err && errlen) {
       snprintf(err, errlen, "%s", m.c_str());
     }
   };
-  if (!defs || ndefs == 0 || ndefs > 255) {
-    seterr("need 1..255 token definitions");
+  uint32_t limit = r < 256 ? 254 : 255;
+  if (!defs || ndefs == 0 || ndefs > limit || r > 256) {
+    seterr("need 1.." + std::to_string(limit) + " token definitions and a byte below 256");
     return nullptr;
   }
   orc_set *S = new orc_set;
@@ -892,14 +896,34 @@ orc_set *orc_compile(const orc_def *defs, uint32_t ndefs, char *err, size_t errl
       delete S;
       return nullptr;
     }
+    if (r < 256) {
+      // the reserved byte leaves every class: no word of this kind contains it
+      for (Node &nd : ast)
+        if (nd.kind == N_SET) nd.set.w[r >> 6] &= ~((uint64_t)1 << (r & 63));
+    }
     Nfa::Frag f = S->nfa.build(ast, root);
     S->start.push_back(f.start);
     S->final_.push_back(f.end);
     S->prio.push_back(defs[k].priority);
     S->discard.push_back(defs[k].discard ? 1 : 0);
   }
+  if (r < 256) {
+    // the reserved byte's own kind: the one-byte word r
+    std::vector<Node> ast(1);
+    ast[0].kind = N_SET;
+    ast[0].set.add((int)r);
+    Nfa::Frag f = S->nfa.build(ast, 0);
+    S->start.push_back(f.start);
+    S->final_.push_back(f.end);
+    S->prio.push_back(0);
+    S->discard.push_back(r_discard ? 1 : 0);
+  }
   S->mark.assign(S->nfa.st.size(), 0);
   return S;
+}
+
+orc_set *orc_compile(const orc_def *defs, uint32_t ndefs, char *err, size_t errlen) {
+  return orc_compile_framed(defs, ndefs, 256, 0, err, errlen);
 }
 
 void orc_free(orc_set *s) { delete s; }

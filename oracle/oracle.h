@@ -52,6 +52,11 @@ typedef struct orc_set orc_set;
 /* Parse every pattern and build its Thompson NFA.  NULL on error (message in
  * err).  The set is immutable afterwards. */
 orc_set *orc_compile(const orc_def *defs, uint32_t ndefs, char *err, size_t errlen);
+/* Framing at the producer (Section 7.1): the byte r is reserved -- removed from every
+ * byte class of every pattern, so no token contains it -- and given a kind of its own,
+ * kind ndefs, whose only word is r (priority 0, discarded iff r_discard). */
+orc_set *orc_compile_framed(const orc_def *defs, uint32_t ndefs, uint32_t r, int r_discard, char *err,
+                            size_t errlen);
 void orc_free(orc_set *s);
 uint32_t orc_nkinds(const orc_set *s);
 

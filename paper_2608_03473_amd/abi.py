@@ -67,6 +67,7 @@ def lib():
     P, U8, I32, U32, U64, SZ = C.c_void_p, C.c_uint8, C.c_int32, C.c_uint32, C.c_uint64, C.c_size_t
     sig = {
         "lex_compile": (C.c_int, [P, U32, P, C.c_char_p, SZ]),
+        "lex_compile_framed": (C.c_int, [P, U32, U32, C.c_int, P, C.c_char_p, SZ]),
         "lex_compile_table": (C.c_int, [I32, I32, P, P, P, I32, P, C.c_char_p, SZ]),
         "lex_free": (None, [P]),
         "lex_cert": (C.c_int, [P, C.c_int, C.c_int, P]),
@@ -96,7 +97,7 @@ def check(rc: int, msg: str = ""):
 
 
 def exported_symbols():
-    return sorted(n for n in ("lex_compile", "lex_compile_table", "lex_free", "lex_cert", "lex_info",
+    return sorted(n for n in ("lex_compile", "lex_compile_framed", "lex_compile_table", "lex_free", "lex_cert", "lex_info",
                               "lex_tables", "lex_workspace_size", "lex_plan", "lex_run", "lex_cert_bitmap",
                               "lex_batch_create", "lex_batch_free", "lex_batch_workspace_size",
                               "lex_run_batch"))

@@ -6,10 +6,13 @@ therefore does on the GPU.
     python -m paper_2608_03473_amd.applicability               # the Table 2 transcriptions
     python -m paper_2608_03473_amd.applicability SET.json      # a token set of one's own
     python -m paper_2608_03473_amd.applicability --json ...    # machine-readable
+    python -m paper_2608_03473_amd.applicability --reserve 0x1E  # each set framed by a byte
 
 A token-set file is a JSON list of objects {"name", "pattern", "priority" (default 0),
 "discard" (default false)}; patterns use the library's byte regex dialect.  The sets are
-computed by the library's compiler (lex_cert), the same one every scan uses.
+computed by the library's compiler (lex_cert), the same one every scan uses.  With
+--reserve r every set is first framed by the byte r (Section 7.1: r leaves every pattern
+and becomes a token of its own, lex_compile_framed).
 """
 from __future__ import annotations
 
@@ -52,9 +55,9 @@ def show_bytes(bs) -> str:
     return " ".join(parts)
 
 
-def analyse(defs) -> dict:
+def analyse(defs, reserve: int | None = None) -> dict:
     """Certified and useful sets of both modes, and the scan each mode gets."""
-    lx = Lexer.compile(defs)
+    lx = Lexer.compile(defs) if reserve is None else Lexer.compile_framed(defs, reserve)
     info = lx.info()
     out = {"kinds": info["nkinds"], "rows": info["nrows"], "monotone": bool(info["monotone"])}
     for mode, key in ((abi.LEX_MODE_EXACT, "exact"), (abi.LEX_MODE_DISCARD, "discard")):
@@ -86,7 +89,11 @@ def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("files", nargs="*", help="token-set JSON files (default: the Table 2 transcriptions)")
     ap.add_argument("--json", action="store_true", help="one JSON object per token set")
+    ap.add_argument("--reserve", type=lambda v: int(v, 0), default=None,
+                    help="frame every set by this byte (e.g. 0x1E) before analysing it")
     args = ap.parse_args(argv)
+    if args.reserve is not None and not 0 <= args.reserve <= 255:
+        ap.error("--reserve takes a byte value 0..255")
     if args.files:
         sets = [(f, None, _load(f)) for f in args.files]
     else:
@@ -94,7 +101,9 @@ def main(argv=None) -> int:
 
         sets = [(name, what, [d.as_tuple() for d in getattr(T, name)]) for name, what in TABLE2]
     for name, what, defs in sets:
-        r = analyse(defs)
+        r = analyse(defs, args.reserve)
+        if args.reserve is not None:
+            name = f"{name} framed by {show_bytes([args.reserve])}"
         if args.json:
             print(json.dumps({"set": name, **({"about": what} if what else {}), **r}))
             continue

@@ -26,6 +26,7 @@ namespace {
 struct Set256 {
   uint32_t w[8] = {0};
   void on(unsigned b) { w[b >> 5] |= 1u << (b & 31); }
+  void off(unsigned b) { w[b >> 5] &= ~(1u << (b & 31)); }
   bool in(unsigned b) const { return (w[b >> 5] >> (b & 31)) & 1u; }
   void span(unsigned a, unsigned z) {
     for (unsigned b = a; b <= z; ++b) on(b);
@@ -722,6 +723,9 @@ bool compile_defs(const std::vector<TokDef> &defs, Compiled &R, std::string &err
       err = "definition " + std::to_string(k) + ": " + parser.error();
       return false;
     }
+    if (defs[k].exclude >= 0)
+      for (Re &x : tree)
+        if (x.op == Re::kSet) x.set.off((unsigned)defs[k].exclude);
     if (!glushkov(tree, root, (int)k, P, kinds[k])) {
       err = "definition " + std::to_string(k) + ": pattern too large";
       return false;

@@ -75,6 +75,9 @@ struct TokDef {
   std::string pattern;
   int32_t priority = 0;
   bool discard = false;
+  // A byte taken out of every byte class of the pattern (-1: none), so that no word of
+  // this kind contains it: the reservation of a framing byte (Section 7.1).
+  int exclude = -1;
 };
 
 // Returns false and sets err on a syntax error or a limit violation.

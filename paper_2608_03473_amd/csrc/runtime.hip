@@ -214,6 +214,32 @@ int resolve(const lex_dfa *d, uint64_t n, int mode, const lex_run_opts *o, Resol
   return LEX_OK;
 }
 
+// Definitions of the C-ABI into the compiler's form; exclude is the reserved byte or -1.
+int compile_into(const lex_tokdef *defs, uint32_t ndefs, int exclude, const lexc::TokDef *extra,
+                 lex_dfa **out, char *err, size_t errlen) {
+  std::vector<lexc::TokDef> v(ndefs);
+  for (uint32_t i = 0; i < ndefs; ++i) {
+    if (!defs[i].pattern) {
+      set_err(err, errlen, "null pattern");
+      return LEX_EINVAL;
+    }
+    v[i].pattern = defs[i].pattern;
+    v[i].priority = defs[i].priority;
+    v[i].discard = defs[i].discard != 0;
+    v[i].exclude = exclude;
+  }
+  if (extra) v.push_back(*extra);
+  lex_dfa *d = new lex_dfa;
+  std::string msg;
+  if (!lexc::compile_defs(v, d->c, msg)) {
+    set_err(err, errlen, msg);
+    delete d;
+    return msg.find("exceeds") != std::string::npos || msg.find("too") != std::string::npos ? LEX_ELIMIT
+                                                                                            : LEX_ESYNTAX;
+  }
+  return finish_compile(d, out, err, errlen);
+}
+
 }  // namespace
 
 extern "C" {
@@ -228,25 +254,26 @@ int lex_compile(const lex_tokdef *defs, uint32_t ndefs, lex_dfa **out, char *err
     set_err(err, errlen, "at most 255 token definitions");
     return LEX_ELIMIT;
   }
-  std::vector<lexc::TokDef> v(ndefs);
-  for (uint32_t i = 0; i < ndefs; ++i) {
-    if (!defs[i].pattern) {
-      set_err(err, errlen, "null pattern");
-      return LEX_EINVAL;
-    }
-    v[i].pattern = defs[i].pattern;
-    v[i].priority = defs[i].priority;
-    v[i].discard = defs[i].discard != 0;
+  return compile_into(defs, ndefs, -1, nullptr, out, err, errlen);
+}
+
+int lex_compile_framed(const lex_tokdef *defs, uint32_t ndefs, uint32_t reserved, int reserved_discard,
+                       lex_dfa **out, char *err, size_t errlen) {
+  if (!defs || !out || ndefs == 0 || reserved > 255) {
+    set_err(err, errlen, "null argument, no definitions or a reserved byte above 255");
+    return LEX_EINVAL;
   }
-  lex_dfa *d = new lex_dfa;
-  std::string msg;
-  if (!lexc::compile_defs(v, d->c, msg)) {
-    set_err(err, errlen, msg);
-    delete d;
-    return msg.find("exceeds") != std::string::npos || msg.find("too") != std::string::npos ? LEX_ELIMIT
-                                                                                            : LEX_ESYNTAX;
+  *out = nullptr;
+  if (ndefs > 254) {
+    set_err(err, errlen, "at most 254 token definitions besides the reserved byte's");
+    return LEX_ELIMIT;
   }
-  return finish_compile(d, out, err, errlen);
+  char pat[8];
+  snprintf(pat, sizeof pat, "\\x%02X", reserved);
+  lexc::TokDef rs;
+  rs.pattern = pat;
+  rs.discard = reserved_discard != 0;
+  return compile_into(defs, ndefs, (int)reserved, &rs, out, err, errlen);
 }
 
 int lex_compile_table(int32_t nstates, int32_t q0, const int32_t *next, const int32_t *accept,

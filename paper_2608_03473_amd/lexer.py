@@ -56,6 +56,16 @@ class Lexer:
     # ----------------------------------------------------------------- build
     @classmethod
     def compile(cls, defs) -> "Lexer":
+        return cls._compile(defs, None, False)
+
+    @classmethod
+    def compile_framed(cls, defs, reserved: int = 0x1E, reserved_discard: bool = False) -> "Lexer":
+        """The set framed by a reserved byte (Section 7.1): the byte is taken out of every
+        pattern and becomes kind len(defs), a token of its own."""
+        return cls._compile(defs, int(reserved), reserved_discard)
+
+    @classmethod
+    def _compile(cls, defs, reserved, reserved_discard) -> "Lexer":
         L = abi.lib()
         nd = _norm_defs(defs)
         arr = (abi.TokDef * len(nd))()
@@ -67,8 +77,13 @@ class Lexer:
             arr[i].discard = 1 if dc else 0
         h = C.c_void_p()
         err = C.create_string_buffer(512)
-        rc = L.lex_compile(arr, len(nd), C.byref(h), err, 512)
+        if reserved is None:
+            rc = L.lex_compile(arr, len(nd), C.byref(h), err, 512)
+        else:
+            rc = L.lex_compile_framed(arr, len(nd), reserved, 1 if reserved_discard else 0, C.byref(h), err, 512)
         abi.check(rc, err.value.decode("latin-1"))
+        if reserved is not None:
+            nd = list(nd) + [(("\\x%02X" % reserved).encode(), 0, bool(reserved_discard))]
         return cls(h, len(nd), nd)
 
     @classmethod

@@ -51,6 +51,33 @@ def test_host_side_argument_checks():
     assert lx.workspace_size(1 << 20, 0) > 0
 
 
+def test_framed_compile_checks():
+    """lex_compile_framed (Section 7.1): argument checks, the reserved byte's kind, and the
+    certified plan of a framed C-like-B set (no hybrid plan)."""
+    L = P.lib()
+    defs = T.as_tuples(T.CLIKE_B)
+    arr = (P.abi.TokDef * len(defs))()
+    keep = [p.encode() for p, _, _ in defs]
+    for i, (p, pr, dc) in enumerate(defs):
+        arr[i].pattern, arr[i].priority, arr[i].discard = keep[i], pr, int(dc)
+    h = C.c_void_p()
+    assert L.lex_compile_framed(arr, len(defs), 256, 0, C.byref(h), None, 0) == P.LEX_EINVAL
+    assert L.lex_compile_framed(None, 1, 0x1E, 0, C.byref(h), None, 0) == P.LEX_EINVAL
+    many = (P.abi.TokDef * 255)()
+    for i in range(255):
+        many[i].pattern = b"a"
+    assert L.lex_compile_framed(many, 255, 0x1E, 0, C.byref(h), None, 0) == P.LEX_ELIMIT
+    lx = P.Lexer.compile_framed(defs)
+    assert lx.info()["nkinds"] == len(defs) + 1
+    for mode in (P.LEX_MODE_EXACT, P.LEX_MODE_DISCARD):
+        assert lx.cert(mode) == {0x1E}
+        assert lx.plan(64 << 20, mode)["hybrid"] == 0
+        assert P.Lexer.compile(defs).plan(64 << 20, mode)["hybrid"] == 1
+    # a rule that was the reserved byte alone keeps a valid, empty language
+    lx = P.Lexer.compile_framed([(r"\x1E", 0, False), (r"[a-z]+", 0, False)])
+    assert lx.cert() == {0x1E}
+
+
 def test_plan_query():
     """lex_plan reports what lex_run would use: one pass by default where the windowed emit
     applies (256-lane workgroups), the fused path otherwise, the pipeline when asked."""

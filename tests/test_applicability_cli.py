@@ -48,3 +48,20 @@ def test_token_set_file(tmp_path, capsys):
     bad.write_text(json.dumps({"pattern": "a"}))
     with pytest.raises(ValueError):
         applicability.main([str(bad)])
+
+
+def test_reserved_byte_framing(capsys):
+    """--reserve 0x1E (Section 7.1): the block-comment row, refused in both modes, certifies
+    the reserved byte in both once framed, and its scans split at it."""
+    assert applicability.main(["--json", "--reserve", "0x1E"]) == 0
+    got = {}
+    for line in capsys.readouterr().out.splitlines():
+        r = json.loads(line)
+        got[r["set"]] = r
+    row = got["TABLE2_ROW4_BCOMMENT framed by \\x1E"]
+    for mode in ("exact", "discard"):
+        assert row[mode]["useful"] == [0x1E] and row[mode]["certified"] == [0x1E]
+        assert row[mode]["scan"].startswith("splits")
+    # a set that already certified bytes keeps them and adds the reserved one
+    assert 0x1E in got["TABLE2_ROW1 framed by \\x1E"]["exact"]["useful"]
+    assert len(got["TABLE2_ROW1 framed by \\x1E"]["exact"]["useful"]) > 1

@@ -39,6 +39,24 @@ def test_named_sets(name):
     _agree(P.Lexer.compile(defs), oracle.OracleSet(defs).cert(), name)
 
 
+@pytest.mark.parametrize("reserved", [0x1E, 0x0A, 0x00, 0x2F, 0xFF])
+@pytest.mark.parametrize("name", ["clike_b", "clike_l", "json", "TABLE2_ROW4_BCOMMENT", "TABLE2_ROW2_STR", "UTF8"])
+def test_framed_sets(name, reserved):
+    """Framing at the producer (Section 7.1): the reserved byte leaves every pattern and
+    becomes a kind of its own, on both sides."""
+    defs = T.as_tuples(SETS[name])
+    lx = P.Lexer.compile_framed(defs, reserved)
+    assert lx.info()["nkinds"] == len(defs) + 1
+    _agree(lx, oracle.OracleSet(defs, reserved=reserved).cert(), (name, reserved))
+
+
+def test_framed_random_sets():
+    for seed in range(150):
+        defs = rand_set(seed, "abc")
+        for r in (ord("a"), ord(";")):
+            _agree(P.Lexer.compile_framed(defs, r), oracle.OracleSet(defs, reserved=r).cert(), (defs, r))
+
+
 def test_random_sets():
     for seed in range(400):
         defs = rand_set(seed, "abc")

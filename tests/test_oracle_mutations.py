@@ -3,8 +3,8 @@
 Each case plants one plausible mistake in a copy of oracle.cc (a dropped clause of
 Definition 2 or 3, delta instead of delta+, a missing useful-set filter, a reversed
 tie-break, an off-by-one in longest match, a missing truncation, a mis-seeded closure),
-builds it into a temporary library and runs the pin suite against it: every mutant must
-fail at least one pin.  The real oracle is never modified.
+builds it into a temporary library and runs the pin suite against it (the framing pins for
+the framing mutants): every mutant must fail at least one pin.  The real oracle is never modified.
 """
 import os
 import subprocess
@@ -36,13 +36,20 @@ MUTANTS = {
     "length_off_by_one": ("best = j + 1 - i;", "best = j - i;"),
     "first_not_longest": ("best = j + 1 - i;\n        break;", "best = j + 1 - i;\n        return best;"),
     "no_truncation": ("if (con < hi - lo) return lo + con;", "(void)con;"),
+    # framing at the producer (Section 7.1), held by the framing pins
+    "framing_no_exclusion": ("if (nd.kind == N_SET) nd.set.w[r >> 6] &= ~((uint64_t)1 << (r & 63));",
+                             "(void)nd;", "test_framing.py"),
+    "framing_discard_inverted": ("S->discard.push_back(r_discard ? 1 : 0);",
+                                 "S->discard.push_back(r_discard ? 0 : 1);", "test_framing.py"),
+    "framing_wrong_byte": ("ast[0].set.add((int)r);", "ast[0].set.add((int)r + 1);", "test_framing.py"),
 }
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
 def test_mutant_fails_a_pin(name, tmp_path):
     src = open(os.path.join(ROOT, "oracle", "oracle.cc")).read()
-    a, b = MUTANTS[name]
+    a, b, *target = MUTANTS[name]
+    target = target[0] if target else "test_oracle_pins.py"
     assert a in src, f"mutation site vanished: {name}"
     m = tmp_path / "mutant.cc"
     m.write_text(src.replace(a, b, 1))
@@ -51,6 +58,6 @@ def test_mutant_fails_a_pin(name, tmp_path):
                     "-o", str(lib), str(m)], check=True)
     env = dict(os.environ, ORACLE_LIB_OVERRIDE=str(lib))
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                        os.path.join(ROOT, "tests", target)],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=300)
     assert r.returncode == 1, f"mutant {name} survived the pins:\n{r.stdout[-2000:]}"

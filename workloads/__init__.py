@@ -46,7 +46,7 @@ def _load():
             build()
         lib = C.CDLL(_LIB_PATH)
         P, U64, D = C.c_void_p, C.c_uint64, C.c_double
-        lib.wl_clike.argtypes = [P, U64, U64, C.c_int]
+        lib.wl_clike.argtypes = [P, U64, U64, C.c_int, U64]
         lib.wl_json.argtypes = [P, U64, U64]
         lib.wl_lognormal_sizes.argtypes = [P, U64, D, D, U64, U64, U64]
         lib.wl_uniform.argtypes = [P, U64, U64]
@@ -57,10 +57,11 @@ def _load():
     return _lib
 
 
-def clike(n: int, seed: int, bcomment: bool = False, out: np.ndarray | None = None) -> np.ndarray:
+def clike(n: int, seed: int, bcomment: bool = False, out: np.ndarray | None = None, frame: int = 0) -> np.ndarray:
+    """frame > 0: records of that many lines, each opened by the separator 0x1E."""
     buf = np.empty(n, np.uint8) if out is None else out
     assert buf.dtype == np.uint8 and buf.flags.c_contiguous and buf.size == n
-    _load().wl_clike(buf.ctypes.data, n, seed, 1 if bcomment else 0)
+    _load().wl_clike(buf.ctypes.data, n, seed, 1 if bcomment else 0, int(frame))
     return buf
 
 
@@ -132,5 +133,5 @@ def docs(count: int, seed: int, **kw):
     base = buf.ctypes.data
     for i in range(count):
         lib.wl_clike(base + int(offs[i]), int(sizes[i]), substream(seed, 1000 + i),
-                     1 if sets[i] == DOC_B else 0)
+                     1 if sets[i] == DOC_B else 0, 0)
     return buf, offs, sizes, sets

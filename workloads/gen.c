@@ -83,14 +83,21 @@ static uint8_t printable(rng_t *r) { return (uint8_t)(0x20 + below(r, 0x7F - 0x2
 
 /* One C-like line into o (without its newline).  Returns 0 if it did not fit.
  * Kinds: IDENT .35, INT .15, OP .25, STR .05, LCOMMENT .05 (+ BCOMMENT .05 when
- * block comments are enabled), normalised; a line comment ends the line. */
-static int clike_line(rng_t *r, out_t *o, int bcomment) {
+ * block comments are enabled), normalised; a line comment ends the line.  When *rs is
+ * set and the line has a token, the record separator 0x1E goes right before its first
+ * token (a token boundary: the byte before is the previous line's newline) and *rs is
+ * cleared. */
+static int clike_line(rng_t *r, out_t *o, int bcomment, int *rs) {
   uint64_t k = poisson(r, 8.0);
   const double w[6] = {0.35, 0.15, 0.25, 0.05, 0.05, 0.05};
   const int nk = bcomment ? 6 : 5;
   double tot = 0;
   for (int i = 0; i < nk; ++i) tot += w[i];
   for (uint64_t t = 0; t < k; ++t) {
+    if (!t && *rs) {
+      if (!put(o, 0x1E)) return 0;
+      *rs = 0;
+    }
     if (t) {
       uint64_t sp = 1 + below(r, 4);
       for (uint64_t s = 0; s < sp; ++s)
@@ -161,13 +168,17 @@ static int clike_line(rng_t *r, out_t *o, int bcomment) {
 
 /* C-like corpus of exactly n bytes: lines of Poisson(8) tokens separated by
  * runs of 1-4 spaces/tabs, each line ended by a newline; the tail that cannot
- * hold another whole line is padded with newlines. */
-void wl_clike(uint8_t *buf, uint64_t n, uint64_t seed, int bcomment) {
+ * hold another whole line is padded with newlines.  frame > 0: a framed
+ * document, records of frame lines each opened by 0x1E before their first token
+ * (deferred to the next line that has one); no other byte of the corpus is 0x1E. */
+void wl_clike(uint8_t *buf, uint64_t n, uint64_t seed, int bcomment, uint64_t frame) {
   rng_t r = {seed};
   out_t o = {buf, 0, n};
-  for (;;) {
+  int rs = 0;
+  for (uint64_t line = 0;; ++line) {
     uint64_t mark = o.n;
-    if (!clike_line(&r, &o, bcomment) || !put(&o, '\n')) {
+    if (frame && line % frame == 0) rs = 1;
+    if (!clike_line(&r, &o, bcomment, &rs) || !put(&o, '\n')) {
       o.n = mark;
       break;
     }
