@@ -394,22 +394,82 @@ __device__ __forceinline__ void put(LaneState &L, Ring &r, uint32_t kind, uint32
   else ++L.cnt;
 }
 
+// Loads the 16-byte block starting at in + blk, reading only bytes inside [0, n).
+__device__ __forceinline__ uint4 load_block(const uint8_t *in, int64_t blk, uint32_t n) {
+  if (blk >= 0 && blk + 16 <= (int64_t)n) return *reinterpret_cast<const uint4 *>(in + blk);
+  uint32_t w[4] = {0, 0, 0, 0};
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int64_t q = blk + k;
+    if (q >= 0 && q < (int64_t)n) w[k >> 2] |= (uint32_t)in[q] << (8 * (k & 3));
+  }
+  return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
 // Non-monotone automata: the walk reached FAIL (a dead end after a non-accepting
 // state).  Longest match takes the last accepting position of the current token if
 // there is one: emit it and re-scan from there, byte by byte, up to `upto`; with no
 // accepting position since the token start the scan halts there (SINK).  The guard on
 // fail != sink keeps the loop finite should a monotone table ever reach it.
+//
+// Bounded failed lookahead (Section 9 names the Theta(N^2) cost of naive longest match and
+// its removal by remembering failed (state, position) pairs, as Reps does).  A trace that
+// failed visited, after its last accepting step, only pairs from which no accepting state
+// is reached before FAIL or the end of the re-scan; a re-scan that meets one of them fails
+// the same way, so it stops there.  Up to kMemo failed traces are kept as cursors (position,
+// row), advanced in step with the re-scan and compared at equal positions; cursors that
+// meet merge, a dead one is dropped, and a new trace pushes out the oldest.  On a^N over
+// {a, a+b, ;} a re-scan then stops two bytes in: linear work instead of quadratic.
+constexpr int kMemo = 4;
+
 template <bool EMIT>
 __device__ __forceinline__ void recover(LaneState &L, Ring &r, const Tables &tb, const uint8_t *in, uint32_t upto) {
+  uint32_t cp[kMemo], cr[kMemo];  // cursor positions (kNone: empty) and rows
+#pragma unroll
+  for (int k = 0; k < kMemo; ++k) cp[k] = kNone, cr[k] = 0;
+  const uintptr_t base = reinterpret_cast<uintptr_t>(in);
+  int64_t cb = INT64_MIN;  // position of the cached block (16-aligned in memory)
+  uint4 cv = make_uint4(0, 0, 0, 0);
   while (L.st == tb.fail && tb.fail != tb.sink) {
     if (L.lacc > L.tok) {
+#pragma unroll
+      for (int k = kMemo - 1; k > 0; --k) cp[k] = cp[k - 1], cr[k] = cr[k - 1];
+      cp[0] = L.lacc;  // the trace that just failed, from its last accepting step on
+      cr[0] = L.lrow;
       const uint32_t row = L.lrow >> kRowShift;
       if (tb.info[row] & kInfoCount) put<EMIT>(L, r, tb.kind[row], L.lacc);
       L.tok = L.lacc;
       L.st = tb.start;
       for (uint32_t p = L.tok; p < upto; ++p) {
-        step<EMIT, false>(L, r, tb, in[p], p);
+        // bytes through a 16-byte block held in registers (one load per block, not per byte)
+        const int64_t blk = (int64_t)p - (int64_t)((base + p) & 15);
+        if (blk != cb) {
+          cb = blk;
+          cv = load_block(in, blk, upto);
+        }
+        const uint32_t q = (uint32_t)((int64_t)p - blk);
+        const uint32_t w4 = q < 4 ? cv.x : q < 8 ? cv.y : q < 12 ? cv.z : cv.w;
+        const uint32_t b = (w4 >> (8 * (q & 3))) & 0xFFu;
+        step<EMIT, false>(L, r, tb, b, p);
+        bool join = false;
+#pragma unroll
+        for (int k = 0; k < kMemo; ++k) {
+          if (cp[k] == p) {
+            cr[k] = entry(tb, cr[k], b) & kRowMask;
+            cp[k] = cr[k] == tb.fail ? kNone : p + 1;
+          }
+          join |= cp[k] == p + 1 && cr[k] == L.st;
+        }
+#pragma unroll
+        for (int k = 1; k < kMemo; ++k)
+#pragma unroll
+          for (int j = 0; j < k; ++j)
+            if (cp[k] == cp[j] && cr[k] == cr[j]) cp[k] = kNone;
         if (L.st == tb.fail) break;
+        if (join) {
+          L.st = tb.fail;  // a failed pair: this trace fails as that one did
+          break;
+        }
       }
     } else {
       L.st = tb.sink;
@@ -441,18 +501,6 @@ __device__ __forceinline__ bool finish(LaneState &L, Ring &r, const Tables &tb, 
     }
     L.st = tb.fail;  // end of input after a non-accepting state: fall back
   }
-}
-
-// Loads the 16-byte block starting at in + blk, reading only bytes inside [0, n).
-__device__ __forceinline__ uint4 load_block(const uint8_t *in, int64_t blk, uint32_t n) {
-  if (blk >= 0 && blk + 16 <= (int64_t)n) return *reinterpret_cast<const uint4 *>(in + blk);
-  uint32_t w[4] = {0, 0, 0, 0};
-#pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    const int64_t q = blk + k;
-    if (q >= 0 && q < (int64_t)n) w[k >> 2] |= (uint32_t)in[q] << (8 * (k & 3));
-  }
-  return make_uint4(w[0], w[1], w[2], w[3]);
 }
 
 __device__ __forceinline__ uint32_t byte_of(const uint4 &v, int k) {
@@ -887,7 +935,7 @@ __device__ __forceinline__ CkSink ck_sink(const WalkArgs &a, uint32_t j) {
 
 // CK: record checkpoints for the windowed emit (monotone automata only).
 template <bool MONO, bool FUSED, bool CK>
-__global__ void __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8, 8))) k_count(WalkArgs a) {
+__global__ void __launch_bounds__(1024) k_count(WalkArgs a) {
   const Lds l = carve_lds(a.nrows);
   stage_tables(a, l, FUSED);
   const Tables tb{lds_bytes_of(l.T), l.info, l.kind, a.sink, a.fail, 0};
@@ -1883,7 +1931,12 @@ __device__ void walk_spec(const Tables &tb, const uint8_t *in, uint32_t n, uint3
   const uintptr_t base = reinterpret_cast<uintptr_t>(in);
   int64_t cb = INT64_MIN;  // position of the cached block (16-aligned in memory)
   uint4 cv = make_uint4(0, 0, 0, 0);
-  uint32_t st = tb.start, tok = b, lacc = b;
+  uint32_t st = tb.start, tok = b, lacc = b, lrow = 0;
+  // non-monotone automata: failed traces as cursors, as the lane walk's fallback keeps them
+  uint32_t cp[kMemo], cr[kMemo];
+#pragma unroll
+  for (int k = 0; k < kMemo; ++k) cp[k] = kNone, cr[k] = 0;
+  bool live = false;  // some cursor is set
   rst = kNone;
   mark(b);
   for (uint32_t p = b; p < end;) {
@@ -1894,16 +1947,45 @@ __device__ void walk_spec(const Tables &tb, const uint8_t *in, uint32_t n, uint3
     }
     const uint32_t q = (uint32_t)((int64_t)p - blk);
     const uint32_t w4 = q < 4 ? cv.x : q < 8 ? cv.y : q < 12 ? cv.z : cv.w;
-    const uint32_t e = entry(tb, st, (w4 >> (8 * (q & 3))) & 0xFFu);
+    const uint32_t by = (w4 >> (8 * (q & 3))) & 0xFFu;
+    const uint32_t e = entry(tb, st, by);
     if (e & kEmitBit) {
       tok = p;
       mark(p);
     }
     st = e & kRowMask;
-    if (!MONO && (e & kAccBit)) lacc = p + 1;
+    if (!MONO && (e & kAccBit)) {
+      lacc = p + 1;
+      lrow = st;
+    }
+    if (!MONO && live) {
+      bool join = false;
+      live = false;
+#pragma unroll
+      for (int k = 0; k < kMemo; ++k) {
+        if (cp[k] == p) {
+          cr[k] = entry(tb, cr[k], by) & kRowMask;
+          cp[k] = cr[k] == tb.fail ? kNone : p + 1;
+        }
+        join |= cp[k] == p + 1 && cr[k] == st;
+      }
+#pragma unroll
+      for (int k = 1; k < kMemo; ++k)
+#pragma unroll
+        for (int j = 0; j < k; ++j)
+          if (cp[k] == cp[j] && cr[k] == cr[j]) cp[k] = kNone;
+#pragma unroll
+      for (int k = 0; k < kMemo; ++k) live |= cp[k] != kNone;
+      if (join && st != tb.sink) st = tb.fail;  // a failed pair: fail as that trace did
+    }
     ++p;
     if (st == tb.sink || (!MONO && st == tb.fail)) {
       if (!MONO && st == tb.fail && lacc > tok) {
+#pragma unroll
+        for (int k = kMemo - 1; k > 0; --k) cp[k] = cp[k - 1], cr[k] = cr[k - 1];
+        cp[0] = lacc;  // the failed trace, from its last accepting step on
+        cr[0] = lrow;
+        live = true;
         tok = lacc;  // longest match: the token ends at its last accepting position
       } else {
         rst = tok;  // no token starts at tok: restart one byte on

@@ -20,15 +20,29 @@ class Model:
         self.mono = bool(inf["monotone"])
         self.fail = self.sink if self.mono else (2 + inf["nstates"]) * 256
 
-    def walk(self, w: bytes, s: int, e: int):
-        """Tokens (kind, length, start) written by a lane on [s, e), and its halt offset or None."""
+    def walk(self, w: bytes, s: int, e: int, memo: int = 4, work=None):
+        """Tokens (kind, length, start) written by a lane on [s, e), and its halt offset or None.
+        memo: failed traces kept by the fallback (0: plain re-scans); work: a one-element list
+        that receives the transitions taken (walk, re-scans and failed-trace cursors)."""
         T, out = self.T, []
         st, tok, lacc, lrow = 0, s, s, 0
+        steps = 0
+
+        def nxt(row, b):
+            return (int(T[row + (b ^ ((row >> 8) & 31))]) & ROWMASK) >> 2
 
         def recover(upto):  # non-monotone automata only (FAIL != SINK)
-            nonlocal st, tok, lacc, lrow
+            nonlocal st, tok, lacc, lrow, steps
+            # failed traces as cursors [position, row]: every (row, position) pair a trace visits
+            # after its last accepting step leads to FAIL, or to the end of the slice, without
+            # another accepting state
+            segs = []
             while st == self.fail:
                 if lacc > tok:
+                    if memo:
+                        if len(segs) == memo:
+                            segs.pop(0)
+                        segs.append([lacc, lrow])
                     r = lrow >> 8
                     if self.info[r] & INFO_COUNT:
                         out.append((int(self.kind[r]), lacc - tok, tok))
@@ -36,14 +50,23 @@ class Model:
                     p = tok
                     while p < upto:
                         step(w[p], p)
+                        for c in segs:
+                            if c[0] == p:
+                                c[0], c[1] = p + 1, nxt(c[1], w[p])
+                                steps += 1
+                        segs = [c for i, c in enumerate(segs) if c[1] != self.fail and c not in segs[:i]]
                         p += 1
                         if st == self.fail:
+                            break
+                        if any(c[0] == p and c[1] == st for c in segs):
+                            st = self.fail  # a failed pair: this trace fails as that one did
                             break
                 else:
                     st = self.sink
 
         def step(b, p):
-            nonlocal st, tok, lacc, lrow
+            nonlocal st, tok, lacc, lrow, steps
+            steps += 1
             x = int(T[st + (b ^ ((st >> 8) & 31))])
             if x & EMIT:
                 if x & COUNT:
@@ -58,6 +81,8 @@ class Model:
             if not self.mono and st == self.fail:
                 recover(p + 1)
         while True:
+            if work is not None:
+                work[0] = steps
             if not self.mono and st == self.fail:
                 recover(e)
                 continue

@@ -149,3 +149,48 @@ def test_hybrid_plan_model():
     w = bytes(workloads.clike(3000, 10)) + b"\n/* " + b"x" * 5000 + b" */\n" + bytes(workloads.clike(6000, 11))
     assert oc.lex(w, discard=True)[2] == len(w)
     assert hostmodel.spec_plan(m, w, 4096, 2048) is None
+
+
+def test_failed_lookahead_memo():
+    """Bounded failed lookahead (the Θ(N²) pathology of naive longest match, removed by
+    remembering failed (state, position) pairs as Reps does): the fallback keeps up to four
+    failed traces as cursors and stops a re-scan that meets one.  Same tokens as the oracle
+    with any number of cursors; linear work on the paper's a^N example over {a, a+b, ;} and
+    on unterminated block comments, where plain re-scans are quadratic."""
+    rng = random.Random(4)
+    for seed in range(120):
+        defs = rand_set(seed, "abc")
+        lx = P.Lexer.compile(defs)
+        if lx.info()["monotone"]:
+            continue
+        oc = oracle.OracleSet(defs)
+        m = hostmodel.Model(lx, P.LEX_MODE_EXACT)
+        for _ in range(12):
+            w = bytes(rng.choice(b"abc") for _ in range(rng.randint(0, 40)))
+            k, l, offs, con = oc.lex(w, offsets=True)
+            want = (list(zip(k.tolist(), l.tolist(), offs.tolist())), None if con == len(w) else con)
+            for memo in (0, 1, 2, 4):
+                assert m.walk(w, 0, len(w), memo=memo) == want, (defs, w, memo)
+
+    ex = [("a", 0, False), ("a+b", 0, False), (";", 0, False)]
+    m = hostmodel.Model(P.Lexer.compile(ex), P.LEX_MODE_EXACT)
+    for n in (400, 1600):
+        w = b"a" * n
+        plain, memo = [0], [0]
+        got0, _ = m.walk(w, 0, n, memo=0, work=plain)
+        got4, _ = m.walk(w, 0, n, memo=4, work=memo)
+        assert got0 == got4 == [(0, 1, i) for i in range(n)]
+        assert plain[0] > n * n // 4 and memo[0] < 6 * n, (n, plain[0], memo[0])
+
+    cb = T.as_tuples(T.CLIKE_B)
+    oc = oracle.OracleSet(cb)
+    m = hostmodel.Model(P.Lexer.compile(cb), P.LEX_MODE_EXACT)
+    for unit in (b"/*a", b"/*a\n", b'/* "x', b"/**a"):
+        w = unit * 300
+        k, l, offs, con = oc.lex(w, offsets=True)
+        plain, memo = [0], [0]
+        got0 = m.walk(w, 0, len(w), memo=0, work=plain)
+        got4 = m.walk(w, 0, len(w), memo=4, work=memo)
+        want = (list(zip(k.tolist(), l.tolist(), offs.tolist())), None if con == len(w) else con)
+        assert got0 == got4 == want, unit
+        assert memo[0] < 8 * len(w), (unit, plain[0], memo[0])
