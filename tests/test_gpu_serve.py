@@ -74,3 +74,27 @@ def test_slots_overlap_under_load():
     print(f"[case] serving load: {metrics}", flush=True)
     assert metrics["errors"] == 0 and metrics["max_slots_busy"] >= 2
     assert metrics["p50_us"] is not None and metrics["p99_us"] >= metrics["p50_us"]
+
+
+def test_large_batches_split_by_views():
+    """Many requests admitted at once go out as large batches (gathered and split with one
+    numpy call each, requests holding views of the batch's tokens): every result is the
+    oracle's scan of its request."""
+    from paper_2608_03473_amd import serve
+
+    pool = serve.make_pool(30, 13, median=2048, hi=64 << 10)
+    server = serve.Server(serve.instances(), budget_bytes=1 << 30, slots=2, max_docs=64, slot_cap=4 << 20)
+    for i, (inst, b) in enumerate(pool):
+        server.admit(serve.Request(i, inst, b, 0.0), 0.0)
+    done = []
+    while server.busy():
+        done += server.step(lambda: 0.0)
+    print(f"[case] serving large batches: sizes {server.batch_sizes}", flush=True)
+    assert len(done) == len(pool) and max(server.batch_sizes) > serve._SMALL
+    orcs = [oracle.OracleSet(T.as_tuples(d)) for d, _ in SETS]
+    for r in done:
+        defs, disc = SETS[r.inst]
+        k, l, con = orcs[r.inst].lex(bytes(r.payload), discard=disc)
+        assert r.status == 0 and r.error_offset == con and r.ntokens == len(k), r.rid
+        np.testing.assert_array_equal(r.kinds, k, err_msg=f"request {r.rid}")
+        np.testing.assert_array_equal(r.lens, l, err_msg=f"request {r.rid}")
