@@ -580,10 +580,13 @@ __device__ __forceinline__ void block16(LaneState &L, Ring &r, const Tables &tb,
     L.tok = m ? blk + 15 - __clz(m) : L.tok;
     return;
   }
-  if (EMIT && MONO && FAST) {
+  if (EMIT && FAST) {
     {
-      // packed emit walk: no branch per byte; chunks are split off after 8 and 16 bytes
-      uint32_t st = L.st, tok = L.tok, o = r.o;
+      // packed emit walk: no branch per byte; chunks are split off after 8 and 16 bytes.
+      // Non-monotone automata also track the last accepting step; a FAIL reached inside
+      // the block stays in the FAIL row (no flags) to the block's end, and the caller's
+      // fallback re-scans from that step.
+      uint32_t st = L.st, tok = L.tok, o = r.o, lacc = L.lacc, lrow = L.lrow;
 #pragma unroll
       for (int k = 0; k < 16; ++k) {
         const uint32_t p = blk + k;
@@ -592,6 +595,10 @@ __device__ __forceinline__ void block16(LaneState &L, Ring &r, const Tables &tb,
         o += e & kCountBit;
         tok = (e & kEmitBit) ? p : tok;
         st = e & kRowMask;
+        if (!MONO) {
+          lacc = (e & kAccBit) ? p + 1 : lacc;
+          lrow = (e & kAccBit) ? st : lrow;
+        }
         if (k == 7 || k == 15) {
           r.o = o;
           ring_maybe_split(r);
@@ -599,6 +606,10 @@ __device__ __forceinline__ void block16(LaneState &L, Ring &r, const Tables &tb,
       }
       L.st = st;
       L.tok = tok;
+      if (!MONO) {
+        L.lacc = lacc;
+        L.lrow = lrow;
+      }
       return;
     }
   }
@@ -2262,7 +2273,8 @@ __global__ void __launch_bounds__(256) k_bemit(BatchArgs a) {
       if (!r.direct && !r.offs) walk<true, true, true>(L, r, tb, src, doc.length, s, e);
       else walk<true, true, false>(L, r, tb, src, doc.length, s, e);
     } else {
-      walk<true, false, false>(L, r, tb, src, doc.length, s, e);
+      if (!r.direct && !r.offs) walk<true, false, true>(L, r, tb, src, doc.length, s, e);
+      else walk<true, false, false>(L, r, tb, src, doc.length, s, e);
     }
     ring_flush_tail(r);
     if (j == halt) a.res[d].error_offset = L.tok;  // the halt offset, relative to the document

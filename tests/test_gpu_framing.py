@@ -36,17 +36,18 @@ def sets():
     }
 
 
-def check(lx, oc, buf, mode, opts=None, label=""):
+def check(lx, oc, buf, mode, opts=None, label="", offsets=True):
     print(f"[case] framed C-like-B mode={mode} n={len(buf)} "
-          f"opts={opts and (opts.lane_bytes, opts.path)} {label}", flush=True)
+          f"opts={opts and (opts.lane_bytes, opts.path)} offsets={offsets} {label}", flush=True)
     k, l, o, con = oc.lex(bytes(buf), discard=bool(mode & 1), offsets=True)
-    r = lx.run(torch.from_numpy(np.array(buf, np.uint8, copy=True)).cuda(), mode=mode, offsets=True, opts=opts)
+    r = lx.run(torch.from_numpy(np.array(buf, np.uint8, copy=True)).cuda(), mode=mode, offsets=offsets, opts=opts)
     assert r.status == 0
     assert r.error_offset == con, (r.error_offset, con)
     assert r.ntokens == len(k), (r.ntokens, len(k))
     np.testing.assert_array_equal(r.kinds.cpu().numpy(), k)
     np.testing.assert_array_equal(r.lens.cpu().numpy().view(np.uint32), l)
-    np.testing.assert_array_equal(r.offsets.cpu().numpy().astype(np.uint64), o)
+    if offsets:
+        np.testing.assert_array_equal(r.offsets.cpu().numpy().astype(np.uint64), o)
     return r
 
 
@@ -63,6 +64,21 @@ def test_framed_document_splits_at_the_separator(sets, mode, path, lane):
     r = check(lx, oc, DOC, mode, P.RunOpts(lane_bytes=lane, path=path))
     assert r.nslices > 1
     assert int((r.kinds.cpu().numpy() == len(DEFS)).sum()) == int((DOC == RS).sum())
+
+
+@pytest.mark.parametrize("mode", [P.LEX_MODE_EXACT, P.LEX_MODE_DISCARD])
+@pytest.mark.parametrize("path", [1, 2])
+def test_framed_without_offsets(sets, mode, path):
+    """Kinds and lengths only: the lane emit's packed walk (no branch per byte), which
+    non-monotone automata take with the last accepting step tracked and the fallback after
+    each block; separators anywhere, so comments and strings are cut and fall back."""
+    lx, oc = sets["lx"], sets["oc"]
+    r = check(lx, oc, DOC, mode, P.RunOpts(lane_bytes=256, path=path), offsets=False)
+    assert r.nslices > 1
+    rng = np.random.default_rng(8)
+    w = workloads.clike(400000, 14, bcomment=True).copy()
+    w[rng.choice(w.size, 900, replace=False)] = RS
+    check(lx, oc, w, mode, P.RunOpts(lane_bytes=64, path=path), "separator anywhere", offsets=False)
 
 
 def test_separator_discarded(sets):

@@ -221,6 +221,9 @@ def test_json_discard(path):
     # non-monotone fallbacks inside many lanes
     bad = np.frombuffer(b"\n".join([b"1.", b"[1.5e]", b"-", b"1e+", b"tru", b"{\"a\": 1.}"] * 50), np.uint8)
     check("json", bad, P.LEX_MODE_DISCARD, opts(16, path))
+    # kinds and lengths only (the lane emit's packed walk), fallbacks included
+    check("json", js, P.LEX_MODE_DISCARD, opts(256, path), offsets=False)
+    check("json", bad, P.LEX_MODE_DISCARD, opts(16, path), offsets=False)
 
 
 def test_clike_b_refused():
