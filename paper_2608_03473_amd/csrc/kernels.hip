@@ -365,6 +365,7 @@ struct LaneState {
   uint32_t lacc;  // position after the last accepting step (non-monotone)
   uint32_t lrow;  // row byte offset of that accepting state
   uint32_t cnt;   // counted tokens (count walk)
+  uint32_t fb;    // the walk fell back at least once (non-monotone)
 };
 
 // One transition on byte b at position p.  Emit walk: the step writes the candidate
@@ -430,6 +431,7 @@ __device__ __forceinline__ void recover(LaneState &L, Ring &r, const Tables &tb,
   const uintptr_t base = reinterpret_cast<uintptr_t>(in);
   int64_t cb = INT64_MIN;  // position of the cached block (16-aligned in memory)
   uint4 cv = make_uint4(0, 0, 0, 0);
+  L.fb = 1;
   while (L.st == tb.fail && tb.fail != tb.sink) {
     if (L.lacc > L.tok) {
 #pragma unroll
@@ -630,6 +632,7 @@ __device__ __forceinline__ bool walk(LaneState &L, Ring &r, const Tables &tb, co
   L.tok = s;
   L.lacc = s;
   L.lrow = tb.start;
+  L.fb = 0;
   if (s >= e) return false;
   const int64_t mis = (int64_t)(reinterpret_cast<uintptr_t>(in + s) & 15);
   int64_t b0 = (int64_t)s - mis;
@@ -736,6 +739,7 @@ __device__ __forceinline__ bool walk_lines(LaneState &L, Ring &r, const Tables &
   L.lacc = s;
   L.lrow = tb.start;
   L.cnt = 0;
+  L.fb = 0;
   live = live && s < e;
   const int64_t mis = (int64_t)(reinterpret_cast<uintptr_t>(in) & 127);
   const int64_t P0 = (((int64_t)s + mis) & ~int64_t(127)) - mis;  // the line holding s
@@ -967,8 +971,14 @@ __global__ void __launch_bounds__(1024) k_count(WalkArgs a) {
     // checkpoints hold the count in 24 bits: after a longer slice the windowed emit
     // stands down for the whole scan
     if (CK) big = active && e - s >= (1u << 24);
-  } else if (active) {
-    halted = walk<false, false, false>(L, r, tb, a.in, a.n, s, e);
+  } else {
+    // non-monotone automata: checkpoints as above; they describe the serial scan only while
+    // the lane never fell back (a re-scan revisits positions whose checkpoints the first
+    // pass wrote), so a fallback stands the windowed emit down like a long slice
+    CkSink ck{};
+    if (CK) ck = ck_sink(a, j);
+    if (active) halted = walk<false, false, false, CK>(L, r, tb, a.in, a.n, s, e, ck);
+    if (CK) big = active && (e - s >= (1u << 24) || L.fb);
   }
   if (active && FUSED) {
     a.cuts[j] = s;
@@ -2535,9 +2545,10 @@ static hipError_t count_scan_emit(const DevTable &t, const WalkArgs &a0, const P
   WalkArgs a = a0;
   const size_t smem_c = lds_bytes(t.nrows, (int)p.block, false);
   const size_t smem_e = lds_bytes(t.nrows, (int)p.block, true);
-  const bool win = p.windowed && t.monotone;
+  const bool win = p.windowed;
   mark(ev, 1, s);
-  if (win) k_count<true, FUSED, true><<<p.nblocks, p.block, smem_c, s>>>(a);
+  if (win && t.monotone) k_count<true, FUSED, true><<<p.nblocks, p.block, smem_c, s>>>(a);
+  else if (win) k_count<false, FUSED, true><<<p.nblocks, p.block, smem_c, s>>>(a);
   else if (t.monotone) k_count<true, FUSED, false><<<p.nblocks, p.block, smem_c, s>>>(a);
   else k_count<false, FUSED, false><<<p.nblocks, p.block, smem_c, s>>>(a);
   hipError_t e = hipGetLastError();

@@ -194,3 +194,32 @@ def test_failed_lookahead_memo():
         want = (list(zip(k.tolist(), l.tolist(), offs.tolist())), None if con == len(w) else con)
         assert got0 == got4 == want, unit
         assert memo[0] < 8 * len(w), (unit, plain[0], memo[0])
+
+
+def test_windowed_emit_model_nonmonotone():
+    """The windowed emit on non-monotone automata (framed C-like-B, JSON, exact mode): a scan
+    in which no slice falls back walks the serial trace in every window, so the windowed
+    emit's tokens are the oracle's; a scan with a fallback stands it down (the model returns
+    None, the library runs the lane emit)."""
+    fr = T.as_tuples(T.CLIKE_B)
+    cases = [(P.Lexer.compile_framed(fr), oracle.OracleSet(fr, reserved=0x1E),
+              bytes(workloads.clike(30000, 7, bcomment=True, frame=3))),
+             (P.Lexer.compile(T.as_tuples(T.JSON)), oracle.OracleSet(T.as_tuples(T.JSON)),
+              bytes(workloads.json(30000, 8)))]
+    for lx, oc, w in cases:
+        assert not lx.info()["monotone"]
+        m = hostmodel.Model(lx, P.LEX_MODE_EXACT)
+        k, l, offs, con = oc.lex(w, offsets=True)
+        want = (k.tolist(), l.tolist(), offs.tolist())
+        cert = lx.cert(P.LEX_MODE_EXACT)
+        for lane in (64, 1024):
+            cuts = hostmodel.plan_cuts(w, cert, lane)
+            for starts, ends in [(cuts[:-1], cuts[1:]), hostmodel.plan_fused(w, cert, lane)]:
+                for base in (0, 5):
+                    assert hostmodel.windowed(m, w, starts, ends, lane, base, 4, 1280) == want, lane
+    # a fallback inside a slice (an unterminated comment cut by a separator): stood down
+    lx, oc, w = cases[0]
+    bad = w[:5000] + b"/* x" + bytes([0x1E]) + w[5000:]
+    cert = lx.cert(P.LEX_MODE_EXACT)
+    cuts = hostmodel.plan_cuts(bad, cert, 256)
+    assert hostmodel.windowed(hostmodel.Model(lx, P.LEX_MODE_EXACT), bad, cuts[:-1], cuts[1:], 256, 0) is None
