@@ -290,3 +290,33 @@ def test_random_sets_short_strings():
                 assert r.error_offset == con and r.ntokens == len(k), (defs, w, mode)
                 np.testing.assert_array_equal(r.kinds.cpu().numpy(), k)
                 np.testing.assert_array_equal(r.lens.cpu().numpy().view(np.uint32), l)
+
+
+def test_random_sets_many_lanes():
+    """Random token sets (monotone or not) with a certified ';' on strings of whole tokens
+    (no fallback: the windowed emit also serves non-monotone sets there) and on random
+    strings (fallbacks and halts: the lane emit), split into many lanes on every path."""
+    from randsets import rand_set
+    rng = random.Random(9)
+    for seed in range(60):
+        defs = rand_set(seed, "abc") + [(";", 0, False)]
+        lx, oc = P.Lexer.compile(defs), oracle.OracleSet(defs)
+        words = []
+        for _ in range(300):
+            w = bytes(rng.choice(b"abc") for _ in range(rng.randint(1, 7)))
+            k, _, con = oc.lex(w)
+            if con == len(w) and len(k) == 1:
+                words.append(w)
+        inputs = [bytes(rng.choice(b"abc;") for _ in range(3000))]
+        if words:
+            inputs.append(b";".join(rng.choice(words) for _ in range(700)))
+        for w in inputs:
+            for mode in (0, 1):
+                k, l, o, con = oc.lex(w, discard=bool(mode), offsets=True)
+                for path in (1, 2, 3):
+                    print(f"[case] random set {seed} n={len(w)} mode={mode} path={path}", flush=True)
+                    r = lx.run(to_dev(np.frombuffer(w, np.uint8)), mode=mode, offsets=True, opts=opts(16, path))
+                    assert r.status == 0 and r.error_offset == con and r.ntokens == len(k), (defs, mode, path)
+                    np.testing.assert_array_equal(r.kinds.cpu().numpy(), k)
+                    np.testing.assert_array_equal(r.lens.cpu().numpy().view(np.uint32), l)
+                    np.testing.assert_array_equal(r.offsets.cpu().numpy().astype(np.uint64), o)

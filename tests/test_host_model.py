@@ -223,3 +223,48 @@ def test_windowed_emit_model_nonmonotone():
     cert = lx.cert(P.LEX_MODE_EXACT)
     cuts = hostmodel.plan_cuts(bad, cert, 256)
     assert hostmodel.windowed(hostmodel.Model(lx, P.LEX_MODE_EXACT), bad, cuts[:-1], cuts[1:], 256, 0) is None
+
+
+def _token_string(oc, rng, pieces=120):
+    """Words the oracle lexes as one token each, joined by ';' (certified, a kind of its
+    own): a scan of it never falls back, since each word's longest match is the word."""
+    words = []
+    for _ in range(400):
+        w = bytes(rng.choice(b"abc") for _ in range(rng.randint(1, 7)))
+        k, l, con = oc.lex(w)
+        if con == len(w) and len(k) == 1:
+            words.append(w)
+    if not words:
+        return None
+    return b";".join(rng.choice(words) for _ in range(pieces))
+
+
+def test_windowed_emit_model_random_sets():
+    """Random token sets (monotone or not) with a certified ';', exact mode, on strings long
+    enough for many lanes: whenever no slice falls back, the windowed emit's tokens are the
+    oracle's, else it stands down.  Strings of whole tokens give non-monotone sets scans
+    without fallbacks; random strings give both outcomes."""
+    rng = random.Random(6)
+    ran = nonmono = 0
+    for seed in range(200):
+        defs = rand_set(seed, "abc") + [(";", 0, False)]
+        lx, oc = P.Lexer.compile(defs), oracle.OracleSet(defs)
+        cert = lx.cert(P.LEX_MODE_EXACT)
+        if not cert:
+            continue
+        m = hostmodel.Model(lx, P.LEX_MODE_EXACT)
+        for w in (_token_string(oc, rng), bytes(rng.choice(b"abc;") for _ in range(600))):
+            if w is None:
+                continue
+            k, l, offs, con = oc.lex(w, offsets=True)
+            if con < len(w):
+                continue
+            want = (k.tolist(), l.tolist(), offs.tolist())
+            for lane in (16, 64):
+                cuts = hostmodel.plan_cuts(w, cert, lane)
+                got = hostmodel.windowed(m, w, cuts[:-1], cuts[1:], lane, 7)
+                if got is not None:
+                    ran += 1
+                    nonmono += not lx.info()["monotone"]
+                    assert got == want, (defs, lane)
+    assert ran > 100 and nonmono > 20, (ran, nonmono)
