@@ -51,7 +51,7 @@ struct Plan {
   // records its state at every 64-byte-aligned address strictly inside a slice; the emit
   // walk then runs one thread per 64-byte window of the input.
   int windowed;
-  uint2 *ck;               // checkpoints: kslots * nlanes, window-in-lane-major
+  uint2 *ck;               // checkpoints: kslots * nlanes, two-window blocks per lane (ck_index)
   uint2 *ck_over;          // window-indexed checkpoints beyond a lane's kslots
   uint32_t kslots;
   int32_t *lnz;            // nlanes: last non-empty lane at or before it in its workgroup, or -1

@@ -539,10 +539,16 @@ __device__ __forceinline__ uint32_t range_word(int64_t lo, int64_t hi, int w) {
 // the byte, the tokens it has counted so far and the start of the token in progress.
 //
 // Storage: a window whose start lies k = (start - j l) / kWin windows into lane j's nominal
-// range [j l, (j + 1) l) keeps its checkpoint at main[k * nlanes + j] when k < kslots, so
-// the lanes of a wave, which cross their k-th windows at about the same step, fill whole
-// cache lines together; the rare windows further out (a slice running far past its lane)
-// go to over[window index].
+// range [j l, (j + 1) l) keeps its checkpoint in main when k < kslots, in blocks of kCkB
+// consecutive windows per lane with the lanes interleaved block by block (ck_index): the
+// lanes of a wave, which cross their k-th windows at about the same step, write nearly
+// contiguous bytes, and the emit, whose 64-window tiles cover one or two lanes, uses kCkB
+// checkpoints of every cache line it reads.  The rare windows further out (a slice running
+// far past its lane) go to over[window index].
+constexpr uint32_t kCkB = 2;
+__host__ __device__ inline size_t ck_index(uint32_t k, uint32_t j, uint32_t nlanes) {
+  return ((size_t)(k / kCkB) * nlanes + j) * kCkB + k % kCkB;
+}
 struct CkSink {
   uint2 *main;      // null: off
   uint2 *over;
@@ -551,11 +557,32 @@ struct CkSink {
   uintptr_t base;   // address of the input
 };
 
-__device__ __forceinline__ void ck_record(const CkSink &c, const LaneState &L, uint32_t blk) {
-  const uint2 v = make_uint2(((L.st >> kRowShift) << 24) | L.cnt, L.tok);
+__device__ __forceinline__ uint2 ck_value(const LaneState &L) {
+  return make_uint2(((L.st >> kRowShift) << 24) | L.cnt, L.tok);
+}
+
+__device__ __forceinline__ void ck_store(const CkSink &c, uint2 v, uint32_t blk) {
   const uint32_t k = (blk - c.jl) / kWin;
-  if (k < c.kslots) c.main[(size_t)k * c.nlanes + c.j] = v;
+  if (k < c.kslots) c.main[ck_index(k, c.j, c.nlanes)] = v;
   else c.over[(blk + c.mis0) / kWin] = v;
+}
+
+__device__ __forceinline__ void ck_record(const CkSink &c, const LaneState &L, uint32_t blk) {
+  ck_store(c, ck_value(L), blk);
+}
+
+// The two window starts of a 128-byte line at blk (a line start, so both lie strictly inside
+// the slice when the first does, r0, or only the second): both checkpoints in one 16-byte
+// store when they form one block of ck_index, else one by one.
+__device__ __forceinline__ void ck_pair(const CkSink &c, bool r0, uint2 c0, const LaneState &L, uint32_t blk) {
+  const uint2 c1 = ck_value(L);
+  const uint32_t k0 = (blk - c.jl) / kWin;
+  if (r0 && k0 % kCkB == 0 && k0 + 1 < c.kslots) {
+    *reinterpret_cast<uint4 *>(c.main + ck_index(k0, c.j, c.nlanes)) = make_uint4(c0.x, c0.y, c1.x, c1.y);
+    return;
+  }
+  if (r0) ck_store(c, c0, blk);
+  ck_store(c, c1, blk + kWin);
 }
 
 __device__ __forceinline__ void ck_maybe(const CkSink &c, const LaneState &L, uint32_t blk) {
@@ -754,9 +781,17 @@ __device__ __forceinline__ bool walk_lines(LaneState &L, Ring &r, const Tables &
     const uint32_t st0 = L.st, cnt0 = L.cnt, tok0 = L.tok;
     const uint32_t blk = (uint32_t)P;  // positions blk + q modulo 2^32
     if (__all(full)) {
+      // the line's two window starts: a pair of checkpoints for one lane (one 16-byte store
+      // when they fill one block of ck_index)
+      uint2 c0 = make_uint2(0, 0);
+      bool r0 = false;
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
-        if (CK && i % 4 == 0 && ck.main && mine && P + 16 * i > (int64_t)s) ck_record(ck, L, blk + 16 * i);
+        if (CK && i == 0 && ck.main && mine && P > (int64_t)s) {
+          c0 = ck_value(L);
+          r0 = true;
+        }
+        if (CK && i == 4 && ck.main && mine) ck_pair(ck, r0, c0, L, blk);
         block16<false, true, false>(L, r, tb, v[i], blk + 16 * i);
       }
     } else {
@@ -1228,7 +1263,7 @@ __device__ __forceinline__ WinMeta win_meta(const WalkArgs &a, const WinR1 &r, u
     return m;
   }
   const uint32_t k = (r.ws - owner * a.lane_bytes) / kWin;
-  const uint2 c = k < a.kslots ? a.ck[(size_t)k * a.nlanes + owner] : a.ck_over[i];
+  const uint2 c = k < a.kslots ? a.ck[ck_index(k, owner, a.nlanes)] : a.ck_over[i];
   m.st = row_state(c.x >> 24);
   m.tok = c.y;
   m.out = base + (c.x & 0xFFFFFFu);
@@ -1514,7 +1549,7 @@ __device__ __forceinline__ WinMeta group_meta(const WalkArgs &a, const GroupLds 
   }
   const uint32_t j = c0 + o;
   const uint32_t k = (W - j * a.lane_bytes) / kWin;
-  const uint2 c = k < a.kslots ? a.ck[(size_t)k * a.nlanes + j] : a.ck_over[i];
+  const uint2 c = k < a.kslots ? a.ck[ck_index(k, j, a.nlanes)] : a.ck_over[i];
   m.st = row_state(c.x >> 24);
   m.tok = c.y;
   m.out = base + (c.x & 0xFFFFFFu);
@@ -2354,7 +2389,7 @@ __global__ void __launch_bounds__(256) k_hcuts(HybridArgs h) {
 uint32_t windows_max(uint32_t n) { return (uint32_t)(((uint64_t)n + 2 * kWin - 1) / kWin); }
 // A lane's nominal range plus four windows of slack (slices usually end within a line
 // of their lane's end).
-uint32_t ck_slots(uint32_t lane_bytes) { return lane_bytes / kWin + 4; }
+uint32_t ck_slots(uint32_t lane_bytes) { return (lane_bytes / kWin + 4 + kCkB - 1) / kCkB * kCkB; }
 
 static size_t carve_layout(uint32_t n, uint32_t lane_bytes, uint32_t block, int pipeline, int windowed, int hybrid,
                            size_t *offs) {
