@@ -1087,15 +1087,16 @@ __global__ void __launch_bounds__(1024) k_scan(uint64_t *__restrict__ blk_sum, c
                                                uint32_t block, const uint32_t *__restrict__ counts,
                                                uint32_t *__restrict__ meta, ResultDev *__restrict__ res, uint64_t cap,
                                                uint32_t n) {
-  __shared__ uint64_t part[1024];
-  __shared__ uint32_t pf[1024], pn[1024];
-  const uint32_t tid = threadIdx.x, nt = blockDim.x;
+  // each thread folds a contiguous range of workgroups; the ranges' sums, minima and maxima
+  // are scanned inclusively within each wave by shuffles, across the waves through LDS
+  __shared__ uint64_t wsum[16];
+  __shared__ uint32_t wf[16], wn[16], any_big;
+  __shared__ int32_t wz[16];
+  const uint32_t tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wid = tid >> 6;
   const uint32_t per = (nblocks + nt - 1) / nt;
   const uint32_t lo = min(nblocks, tid * per), hi = min(nblocks, lo + per);
-  __shared__ uint32_t any_big;
   if (tid == 0) any_big = 0;
   __syncthreads();
-  __shared__ int32_t pz[1024];
   uint64_t s = 0;
   uint32_t f = kNone, ne = 0, bg = 0;
   int32_t z = -1;
@@ -1107,25 +1108,42 @@ __global__ void __launch_bounds__(1024) k_scan(uint64_t *__restrict__ blk_sum, c
     z = max(z, blk_lnz[i]);
   }
   if (bg) atomicOr(&any_big, 1u);
-  part[tid] = s;
-  pf[tid] = f;
-  pn[tid] = ne;
-  pz[tid] = z;
-  __syncthreads();
-  for (uint32_t d = 1; d < nt; d <<= 1) {  // inclusive prefix sums, min, sum, max
-    uint64_t v = tid >= d ? part[tid - d] : 0;
-    uint32_t vf = tid >= d ? pf[tid - d] : kNone;
-    uint32_t vn = tid >= d ? pn[tid - d] : 0;
-    int32_t vz = tid >= d ? pz[tid - d] : -1;
-    __syncthreads();
-    part[tid] += v;
-    pf[tid] = min(pf[tid], vf);
-    pn[tid] += vn;
-    pz[tid] = max(pz[tid], vz);
-    __syncthreads();
+  // inclusive scans within the wave
+  uint64_t is = s;
+  uint32_t iff = f, in = ne;
+  int32_t iz = z;
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint64_t v = __shfl_up(is, d);
+    const uint32_t vf = __shfl_up(iff, d), vn = __shfl_up(in, d);
+    const int32_t vz = __shfl_up(iz, d);
+    if (lane >= (uint32_t)d) {
+      is += v;
+      iff = min(iff, vf);
+      in += vn;
+      iz = max(iz, vz);
+    }
   }
-  uint64_t run = tid ? part[tid - 1] : 0;
-  int32_t zrun = tid ? pz[tid - 1] : -1;
+  if (lane == 63) {
+    wsum[wid] = is;
+    wf[wid] = iff;
+    wn[wid] = in;
+    wz[wid] = iz;
+  }
+  __syncthreads();
+  // the earlier waves' totals
+  uint64_t ps = 0;
+  uint32_t pf = kNone, pn = 0;
+  int32_t pz = -1;
+  for (uint32_t w = 0; w < wid; ++w) {
+    ps += wsum[w];
+    pf = min(pf, wf[w]);
+    pn += wn[w];
+    pz = max(pz, wz[w]);
+  }
+  // exclusive prefixes of this thread's range, written back in place
+  uint64_t run = ps + is - s;
+  int32_t zrun = max(pz, (int32_t)__shfl_up(iz, 1));
+  if (lane == 0) zrun = pz;
   for (uint32_t i = lo; i < hi; ++i) {
     const uint64_t x = blk_sum[i];
     blk_sum[i] = run;
@@ -1135,9 +1153,9 @@ __global__ void __launch_bounds__(1024) k_scan(uint64_t *__restrict__ blk_sum, c
     zrun = max(zrun, y);
   }
   __syncthreads();
-  if (tid == 0) {
-    const uint64_t total = part[nt - 1];
-    const uint32_t first = pf[nt - 1];
+  if (tid == nt - 1) {
+    const uint64_t total = ps + is;
+    const uint32_t first = min(pf, iff);
     uint64_t ntok = total;
     if (first != kNone) {
       // tokens before the halted lane plus those it emitted before halting
@@ -1151,7 +1169,7 @@ __global__ void __launch_bounds__(1024) k_scan(uint64_t *__restrict__ blk_sum, c
     res->ntokens = ntok;
     res->error_offset = n;  // replaced by the halted lane in the emit pass
     res->status = ntok > cap ? -4 : 0;
-    res->nslices = pn[nt - 1];
+    res->nslices = pn + in;
   }
 }
 

@@ -320,3 +320,45 @@ def test_random_sets_many_lanes():
                     np.testing.assert_array_equal(r.kinds.cpu().numpy(), k)
                     np.testing.assert_array_equal(r.lens.cpu().numpy().view(np.uint32), l)
                     np.testing.assert_array_equal(r.offsets.cpu().numpy().astype(np.uint64), o)
+
+
+@pytest.mark.parametrize("path", [0, 1, 2])
+def test_graph_replays_single_buffer(path):
+    """One lex_run captured in a hipGraph (its launches use no memset and allocate nothing)
+    and replayed several times, with other eager scans and synchronisations in between:
+    every replay equals the eager scan."""
+    lx, _ = lexers("clike_l")
+    buf = workloads.clike((4 << 20) + 77, 31)
+    n = buf.size
+    o = opts(0, path)
+    data = to_dev(buf)
+    kinds = torch.empty(n, dtype=torch.uint8, device="cuda")
+    lens = torch.empty(n, dtype=torch.int32, device="cuda")
+    res = torch.zeros(3, dtype=torch.int64, device="cuda")
+    ws = torch.empty(lx.workspace_size(n, 0, o), dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    lx.run_into(data, n, 0, kinds, lens, None, n, res, ws, o, stream)
+    torch.cuda.synchronize()
+    want_res = res.cpu().clone()
+    nt = int(want_res[0])
+    want_k, want_l = kinds[:nt].cpu().clone(), lens[:nt].cpu().clone()
+    print(f"[case] graph replays, path {path}, {nt} tokens", flush=True)
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(stream)
+    with torch.cuda.graph(graph, stream=side):
+        lx.run_into(data, n, 0, kinds, lens, None, n, res, ws, o, torch.cuda.current_stream())
+    other = to_dev(workloads.clike(1 << 20, 32))
+    for rep in range(3):
+        kinds.zero_()
+        lens.zero_()
+        res.zero_()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(res.cpu(), want_res), rep
+        assert torch.equal(kinds[:nt].cpu(), want_k) and torch.equal(lens[:nt].cpu(), want_l), rep
+        # eager work between replays, on other buffers
+        r = lx.run(other, mode=0)
+        assert r.status == 0
+        torch.cuda.synchronize()
