@@ -577,7 +577,7 @@ __device__ __forceinline__ void ck_record(const CkSink &c, const LaneState &L, u
 __device__ __forceinline__ void ck_pair(const CkSink &c, bool r0, uint2 c0, const LaneState &L, uint32_t blk) {
   const uint2 c1 = ck_value(L);
   const uint32_t k0 = (blk - c.jl) / kWin;
-  if (r0 && k0 % kCkB == 0 && k0 + 1 < c.kslots) {
+  if (r0 && k0 % 2 == 0 && k0 + 1 < c.kslots) {  // kCkB is even: k0 and k0 + 1 share a block
     *reinterpret_cast<uint4 *>(c.main + ck_index(k0, c.j, c.nlanes)) = make_uint4(c0.x, c0.y, c1.x, c1.y);
     return;
   }
