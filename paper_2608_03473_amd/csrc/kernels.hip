@@ -366,7 +366,18 @@ struct LaneState {
   uint32_t lrow;  // row byte offset of that accepting state
   uint32_t cnt;   // counted tokens (count walk)
   uint32_t fb;    // the walk fell back at least once (non-monotone)
+  // non-monotone count walk: lrow is left as kLazyRow and recomputed when a fallback needs
+  // it, by walking from lst0, the row at block start lblk, up to lacc
+  uint32_t lblk, lst0;
 };
+constexpr uint32_t kLazyRow = 0xFFFFFFFFu;
+
+// The row after the accepting step at lacc - 1, walked from row st at position blk.
+__device__ __forceinline__ uint32_t rewalk_row(const Tables &tb, const uint8_t *in, uint32_t st, uint32_t blk,
+                                               uint32_t lacc) {
+  for (uint32_t p = blk; p < lacc; ++p) st = entry(tb, st, in[p]) & kRowMask;
+  return st;
+}
 
 // One transition on byte b at position p.  Emit walk: the step writes the candidate
 // token into the next ring slot unconditionally (a later step overwrites it unless the
@@ -434,6 +445,7 @@ __device__ __forceinline__ void recover(LaneState &L, Ring &r, const Tables &tb,
   L.fb = 1;
   while (L.st == tb.fail && tb.fail != tb.sink) {
     if (L.lacc > L.tok) {
+      if (L.lrow == kLazyRow) L.lrow = rewalk_row(tb, in, L.lst0, L.lblk, L.lacc);
 #pragma unroll
       for (int k = kMemo - 1; k > 0; --k) cp[k] = cp[k - 1], cr[k] = cr[k - 1];
       cp[0] = L.lacc;  // the trace that just failed, from its last accepting step on
@@ -593,6 +605,30 @@ __device__ __forceinline__ void ck_maybe(const CkSink &c, const LaneState &L, ui
 // offsets (see Ring), so the emit steps need no branch.
 template <bool EMIT, bool MONO, bool FAST>
 __device__ __forceinline__ void block16(LaneState &L, Ring &r, const Tables &tb, const uint4 &v, uint32_t blk) {
+  if (!EMIT && !MONO) {
+    // count walk of a non-monotone automaton: each step shifts its COUNT and EMIT bits into
+    // m (step k's pair lands in bits 2k, 2k + 1) and its ACC bit into a (bit 16 + k); the
+    // last accepting step's row is recomputed only if a fallback needs it (kLazyRow)
+    uint32_t m = 0, ac = 0, e = L.st;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      e = entry_from(tb, e, byte_of(v, k));
+      m = __builtin_amdgcn_alignbit(e, m, 2);
+      ac = __builtin_amdgcn_alignbit(e >> 7, ac, 1);
+    }
+    const uint32_t st0 = L.st;
+    L.st = e & kRowMask;
+    L.cnt += __builtin_popcount(m & 0x55555555u);
+    const uint32_t me = m & 0xAAAAAAAAu;  // bit 2k + 1: step k emitted
+    L.tok = me ? blk + ((31 - __clz(me)) >> 1) : L.tok;
+    if (ac) {
+      L.lacc = blk + (31 - __clz(ac)) - 15;  // one past the last accepting step
+      L.lrow = kLazyRow;
+      L.lblk = blk;
+      L.lst0 = st0;
+    }
+    return;
+  }
   if (!EMIT && MONO) {
     // count walk of a monotone automaton: the COUNT bits of the 16 steps are shifted
     // into m (bit 0 of each entry lands in bit 31) and popcounted once.
