@@ -959,11 +959,20 @@ __device__ __forceinline__ uint32_t search_cert(const uint8_t *in, uint32_t n, c
                                 uint32_t span, uint32_t none) {
   const uint32_t end = (uint32_t)min<uint64_t>((uint64_t)x + span, n);
   int64_t blk = (int64_t)x - (int64_t)(reinterpret_cast<uintptr_t>(in + x) & 15);
-  for (; blk < (int64_t)end; blk += 16) {
-    uint32_t m = match16(load_block(in, blk, n), ca, lut);
-    if (blk < (int64_t)x) m &= ~0u << (uint32_t)((int64_t)x - blk);       // bytes before x
-    if (blk + 16 > (int64_t)end) m &= (1u << (uint32_t)(end - blk)) - 1;  // bytes at or after end
-    if (m) return (uint32_t)blk + (__ffs(m) - 1);
+  // four 16-byte blocks per step, loaded together: one load latency per 64 bytes searched
+  for (; blk < (int64_t)end; blk += 64) {
+    uint4 v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = load_block(in, blk + 16 * q, n);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t b = blk + 16 * q;
+      if (b >= (int64_t)end) return none;
+      uint32_t m = match16(v[q], ca, lut);
+      if (b < (int64_t)x) m &= ~0u << (uint32_t)((int64_t)x - b);       // bytes before x (first block only)
+      if (b + 16 > (int64_t)end) m &= (1u << (uint32_t)(end - b)) - 1;  // bytes at or after end
+      if (m) return (uint32_t)b + (__ffs(m) - 1);
+    }
   }
   return none;
 }
