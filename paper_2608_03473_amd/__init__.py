@@ -6,7 +6,12 @@ memory and streams.  Importing the package does not touch the GPU; the library i
 on first use and its absence is an error (there is no CPU fallback).
 
     lx = Lexer.compile(defs)                 # defs: [(pattern, priority, discard), ...]
-    kinds, lens, err = lx.run(u8_cuda_tensor, mode=LEX_MODE_EXACT)
+    r = lx.run(u8_cuda_tensor, mode=LEX_MODE_EXACT)   # r.kinds, r.lens, r.ntokens, r.error_offset
+    fx = Lexer.compile_framed(defs, 0x1E)    # the set framed by a reserved byte (Section 7.1)
+    b = Batch([(lx, LEX_MODE_EXACT), ...])   # many documents in one launch sequence
+
+Also here: ``serve`` (the serving loop over batches) and ``applicability`` (certified and
+useful bytes of a token set, per mode).
 """
 from .abi import (LEX_EDEVICE, LEX_EINVAL, LEX_ELIMIT, LEX_EMIT_DEFAULT, LEX_EMIT_LANE,  # noqa: F401
                   LEX_ENOMEM, LEX_EOVERFLOW, LEX_ESYNTAX, LEX_MODE_DISCARD, LEX_MODE_EXACT,
