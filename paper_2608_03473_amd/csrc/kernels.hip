@@ -2050,7 +2050,35 @@ __device__ void walk_spec(const Tables &tb, const uint8_t *in, uint32_t n, uint3
   const uintptr_t base = reinterpret_cast<uintptr_t>(in);
   int64_t cb = INT64_MIN;  // position of the cached block (16-aligned in memory)
   uint4 cv = make_uint4(0, 0, 0, 0);
-  uint32_t st = tb.start, tok = b, lacc = b, lrow = 0;
+  // the token starts of one aligned 16-byte block (bit k: position P + k) into both bitmaps,
+  // a word at a time (positions come in increasing order, as for mark)
+  auto mark_bits = [&](uint32_t mk, uint32_t P) {
+    auto put = [&](uint32_t bits, int64_t off, uint32_t *words, uint32_t &cw, uint32_t &cv) {
+      if (off <= -16 || off >= (int64_t)kSpecX) return;
+      if (off < 0) {
+        bits >>= (uint32_t)(-off);
+        off = 0;
+      }
+      const uint32_t wi = (uint32_t)off >> 5, sh = (uint32_t)off & 31;
+      const uint32_t lo = bits << sh, hi = sh > 16 ? bits >> (32 - sh) : 0;
+      if (lo) {
+        if (wi != cw) {
+          words[cw] = cv;
+          cw = wi;
+          cv = 0;
+        }
+        cv |= lo;
+      }
+      if (hi && wi + 1 < kSpecWords) {
+        words[cw] = cv;
+        cw = wi + 1;
+        cv = hi;
+      }
+    };
+    put(mk, (int64_t)P - b, head, hw, hv);
+    put(mk, (int64_t)P - b2, tail, tw, tv);
+  };
+  uint32_t st = tb.start, tok = b, lacc = b, lrow = 0, lblk = b, lst0 = 0;
   // non-monotone automata: failed traces as cursors, as the lane walk's fallback keeps them
   uint32_t cp[kMemo], cr[kMemo];
 #pragma unroll
@@ -2059,6 +2087,51 @@ __device__ void walk_spec(const Tables &tb, const uint8_t *in, uint32_t n, uint3
   rst = kNone;
   mark(b);
   for (uint32_t p = b; p < end;) {
+    if (!live && ((base + p) & 15) == 0 && p + 16 <= end) {
+      // an aligned block without cursors: 16 steps, their EMIT and ACC bits as masks (bit
+      // 16 + k: step k); a halt or FAIL inside leaves the row there, flagless, to the
+      // block's end, and the restart below acts on it as after the step that caused it
+      const uint4 v = *reinterpret_cast<const uint4 *>(in + p);
+      uint32_t e = st, me = 0, ma = 0;
+      const uint32_t st0 = st;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        e = entry_from(tb, e, byte_of(v, k));
+        me = __builtin_amdgcn_alignbit(e >> 1, me, 1);
+        if (!MONO) ma = __builtin_amdgcn_alignbit(e >> 7, ma, 1);
+      }
+      st = e & kRowMask;
+      if (me) {
+        tok = p + (31 - __clz(me)) - 16;
+        mark_bits(me >> 16, p);
+      }
+      if (!MONO && ma) {
+        lacc = p + (31 - __clz(ma)) - 15;
+        lrow = kLazyRow;  // rebuilt from lst0 at lblk if a restart needs it
+        lblk = p;
+        lst0 = st0;
+      }
+      p += 16;
+      if (st == tb.sink || (!MONO && st == tb.fail)) {
+        if (!MONO && st == tb.fail && lacc > tok) {
+          if (lrow == kLazyRow) lrow = rewalk_row(tb, in, lst0, lblk, lacc);
+#pragma unroll
+          for (int k = kMemo - 1; k > 0; --k) cp[k] = cp[k - 1], cr[k] = cr[k - 1];
+          cp[0] = lacc;  // the failed trace, from its last accepting step on
+          cr[0] = lrow;
+          live = true;
+          tok = lacc;
+        } else {
+          rst = tok;  // no token starts at tok: restart one byte on
+          tok = tok + 1;
+        }
+        p = tok;
+        lacc = tok;
+        st = tb.start;
+        if (p < end) mark(p);
+      }
+      continue;
+    }
     const int64_t blk = (int64_t)p - (int64_t)((base + p) & 15);
     if (blk != cb) {
       cb = blk;
@@ -2100,6 +2173,7 @@ __device__ void walk_spec(const Tables &tb, const uint8_t *in, uint32_t n, uint3
     ++p;
     if (st == tb.sink || (!MONO && st == tb.fail)) {
       if (!MONO && st == tb.fail && lacc > tok) {
+        if (lrow == kLazyRow) lrow = rewalk_row(tb, in, lst0, lblk, lacc);
 #pragma unroll
         for (int k = kMemo - 1; k > 0; --k) cp[k] = cp[k - 1], cr[k] = cr[k - 1];
         cp[0] = lacc;  // the failed trace, from its last accepting step on
