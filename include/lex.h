@@ -149,8 +149,8 @@ int lex_tables(const lex_dfa *dfa, int mode, uint32_t *table, size_t table_entri
  * sub-slice; a scan with a halted slice or a slice of 2^24 bytes or more falls back to the
  * lane emit (one thread per slice) on the device, and so does a scan of a non-monotone
  * automaton (a live edge from an accepting to a non-accepting state) in which some slice
- * fell back to an earlier accepting position, or that runs under the hybrid plan.  One
- * pass needs a monotone automaton.  All write the same outputs.  events:
+ * fell back to an earlier accepting position.  One pass needs a monotone automaton and
+ * certified cuts.  All write the same outputs.  events:
  * optional array of LEX_NPHASES + 1 hipEvent_t (passed as void*, created by the caller)
  * recorded on the scan's stream at the phase boundaries: [0] start, [1] after planning
  * (steps a, b), [2] after the count walk (c), [3] after the scan (d), [4] after the emit

@@ -251,6 +251,34 @@ def test_clike_b_refused():
     assert r.nslices == 2
 
 
+def test_clike_b_refused_exact_windowed():
+    """The same hybrid-plan cases in exact mode, where every token end is counted: the
+    windowed emit runs over the hybrid cuts (a non-monotone automaton: it stands down for a
+    scan in which a slice fell back, and the lane emit writes the tokens)."""
+    lx, _ = lexers("clike_b")
+    cb = workloads.clike(400000, 9, bcomment=True)
+    plan = lx.plan(cb.size, P.LEX_MODE_EXACT)
+    assert plan["hybrid"] == 1 and plan["windowed"] == 1
+    r = check("clike_b", cb, P.LEX_MODE_EXACT, label="hybrid, windowed")
+    assert r.nslices > 50
+    check("clike_b", cb, P.LEX_MODE_EXACT, offsets=False, label="hybrid, windowed, no offsets")
+    bad = np.array(cb[:100000], copy=True)
+    bad[70000:70002] = ord("@")
+    check("clike_b", bad, P.LEX_MODE_EXACT, label="halting")
+    long_comment = np.concatenate([workloads.clike(3000, 11), np.frombuffer(b"\n/* " + b"x" * 5000 + b" */\n", np.uint8),
+                                   workloads.clike(60000, 12)])
+    r = check("clike_b", long_comment, P.LEX_MODE_EXACT, label="long comment across a lane boundary")
+    assert r.nslices == 1
+    for n in (4097, 4096 + 600, 9000):
+        check("clike_b", cb[:n], P.LEX_MODE_EXACT, pad_front=3, label="just over one lane")
+    tail = np.concatenate([workloads.clike(8100, 13, bcomment=True), np.full(300, 10, np.uint8)])
+    r = check("clike_b", tail, P.LEX_MODE_EXACT, label="last token across the last lane's start")
+    assert r.nslices == 2
+    # unterminated comments cut by lane boundaries: fallbacks inside slices
+    w = np.frombuffer(b"/*a" * 3000, np.uint8)  # the oracle re-scans naively: kept short
+    check("clike_b", w, P.LEX_MODE_EXACT, label="fallbacks in every slice")
+
+
 def test_log_planning_workload():
     w = workloads.loglines(1 << 20, 40)
     r = check("log", w, P.LEX_MODE_EXACT, opts(1024, 1))
