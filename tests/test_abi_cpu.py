@@ -135,3 +135,20 @@ def test_batch_argument_checks():
     assert L.lex_batch_workspace_size(None, 10, 1000, None) == 0
     assert L.lex_run_batch(None, None, 0, None, 0, None, None, None, 0, None, None, None, 0, None, None) == P.LEX_EINVAL
     assert np.dtype(P.DOC_DTYPE).itemsize == 16 and np.dtype(P.DOC_RESULT_DTYPE).itemsize == 32
+
+
+def test_size_limit_boundary():
+    """Offsets are 32-bit: n = 2^32 - 16 is the largest input; one byte more is LEX_ELIMIT from
+    the host checks of lex_workspace_size, lex_plan and lex_run (no device work happens; the
+    pointers below are never dereferenced)."""
+    lx = P.Lexer.compile(T.as_tuples(T.CLIKE_L))
+    L = P.lib()
+    top = (1 << 32) - 16
+    assert L.lex_workspace_size(lx._h, top, 0, None) > 0
+    assert lx.plan(top, 0)["path"] in (1, 2, 3)
+    assert L.lex_workspace_size(lx._h, top + 1, 0, None) == 0
+    info = P.abi.PlanInfo()
+    assert L.lex_plan(lx._h, top + 1, 0, None, C.byref(info)) == P.LEX_ELIMIT
+    fake = C.c_void_p(1 << 20)  # 16-byte aligned, never touched
+    rc = L.lex_run(lx._h, fake, top + 1, 0, fake, fake, None, 0, fake, fake, 1 << 20, None, None)
+    assert rc == P.LEX_ELIMIT
