@@ -169,3 +169,27 @@ def test_json_256mib_discard():
     assert not np.isin(kinds, ws).any() and lens.min() >= 1
     assert np.all(starts[1:] >= starts[:-1] + lens[:-1])  # kept tokens disjoint, in order
     sampled_stretches(buf, starts, kinds, lens, oc, True, seed=12)
+
+
+def test_clike_3gib_exact():
+    """Near the size limit: a 3 GiB (plus a ragged 77 bytes) C-like corpus, past 2^31 bytes,
+    in the bench's launch configuration; the same tiling properties and sampled stretches."""
+    n = (3 << 30) + 77
+    buf = workloads.clike(n, 5)
+    defs = T.as_tuples(T.CLIKE_L)
+    lx = P.Lexer.compile(defs)
+    dev = torch.from_numpy(buf).cuda()
+    print(f"[case] C-like-L exact n={n} seed 5", flush=True)
+    r = lx.run(dev, mode=P.LEX_MODE_EXACT, opts=bench_opts())
+    del dev
+    assert r.status == 0 and r.error_offset == n and r.nslices > 40000
+    kinds = r.kinds.cpu().numpy()
+    lens = r.lens.cpu().numpy().view(np.uint32)
+    del r
+    torch.cuda.empty_cache()
+    assert lens.min() >= 1 and int(lens.sum(dtype=np.uint64)) == n
+    assert int(kinds.max()) < len(T.CLIKE_L)
+    starts = np.zeros(lens.size, np.int64)
+    np.cumsum(lens[:-1], out=starts[1:])
+    assert starts[-1] > (1 << 31)  # tokens past 2^31 bytes
+    sampled_stretches(buf, starts, kinds, lens, oracle.OracleSet(defs), False, seed=12)
