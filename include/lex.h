@@ -234,7 +234,9 @@ int lex_batch_create(const lex_dfa *const *dfas, const int32_t *modes, uint32_t 
                      char *err, size_t errlen);
 void lex_batch_free(lex_batch *batch);
 
-/* Workspace for ndocs documents over nbytes bytes (opts: lane_bytes; NULL = defaults). */
+/* Workspace for ndocs documents over nbytes bytes (opts: lane_bytes; NULL = defaults).  A
+ * batch's default lane is 1 KiB, doubled while nbytes / lane exceeds 2^20, up to 4 KiB;
+ * pass the same opts (or the same nbytes with defaults) to lex_run_batch. */
 size_t lex_batch_workspace_size(const lex_batch *batch, uint32_t ndocs, uint64_t nbytes, const lex_run_opts *opts);
 
 /* Scans the ndocs documents of d_docs (device array) over d_bytes[0, nbytes) (device).

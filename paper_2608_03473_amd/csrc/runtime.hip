@@ -481,8 +481,18 @@ void lex_batch_free(lex_batch *b) {
   delete b;
 }
 
-static int batch_lane_bytes(const lex_run_opts *o, uint32_t &lb) {
-  lb = o && o->lane_bytes ? o->lane_bytes : 1024u;
+// Default batch lane: 1 KiB, doubled while the batch would have more than about 1M lanes,
+// up to 4 KiB.  Below that count a lane's fixed costs (plan entry, count, scan slot, emit
+// start) are small beside its walk; above it they dominate, and longer lanes pay (lanes
+// longer than the speculative lane also lengthen the hybrid plan's walks).
+static uint32_t batch_default_lane_bytes(uint64_t nbytes) {
+  uint32_t l = 1024;
+  while (l < 4096 && nbytes / l > (1u << 20)) l <<= 1;
+  return l;
+}
+
+static int batch_lane_bytes(const lex_run_opts *o, uint64_t nbytes, uint32_t &lb) {
+  lb = o && o->lane_bytes ? o->lane_bytes : batch_default_lane_bytes(nbytes);
   if (lb < 16 || (lb & 15)) return LEX_EINVAL;
   if (o && (o->emit || (o->path && o->path != 2))) return LEX_EINVAL;  // the batch plans like path 2
   return LEX_OK;
@@ -490,7 +500,7 @@ static int batch_lane_bytes(const lex_run_opts *o, uint32_t &lb) {
 
 size_t lex_batch_workspace_size(const lex_batch *b, uint32_t ndocs, uint64_t nbytes, const lex_run_opts *opts) {
   uint32_t lb = 0;
-  if (!b || nbytes > 0xFFFFFFF0ull || batch_lane_bytes(opts, lb) != LEX_OK) return 0;
+  if (!b || nbytes > 0xFFFFFFF0ull || batch_lane_bytes(opts, nbytes, lb) != LEX_OK) return 0;
   return lexk::batch_workspace_bytes(ndocs, nbytes, lb);
 }
 
@@ -502,7 +512,7 @@ int lex_run_batch(const lex_batch *b, const uint8_t *d_bytes, uint64_t nbytes, c
   if ((reinterpret_cast<uintptr_t>(d_kinds) | reinterpret_cast<uintptr_t>(d_lens)) & 15) return LEX_EINVAL;
   if (nbytes > 0xFFFFFFF0ull || cap > 0xFFFFFFF0ull) return LEX_ELIMIT;
   uint32_t lb = 0;
-  int rc = batch_lane_bytes(opts, lb);
+  int rc = batch_lane_bytes(opts, nbytes, lb);
   if (rc != LEX_OK) return rc;
   if (ws_bytes < lexk::batch_workspace_bytes(ndocs, nbytes, lb)) return LEX_ELIMIT;
   int dev = -1;

@@ -88,7 +88,7 @@ def check_batch(setup, data, docs, r):
     assert r.ntokens == total and r.nerrors == nerr
 
 
-@pytest.mark.parametrize("lane", [16, 64, 1024])
+@pytest.mark.parametrize("lane", [16, 64, 1024, 4096])
 def test_batch_mixed_instances(setup, lane):
     data, docs = make_docs(400, 7)
     print(f"[case] batch of {docs.size} docs, {data.size} B, lane {lane}", flush=True)

@@ -193,3 +193,43 @@ def test_clike_3gib_exact():
     np.cumsum(lens[:-1], out=starts[1:])
     assert starts[-1] > (1 << 31)  # tokens past 2^31 bytes
     sampled_stretches(buf, starts, kinds, lens, oracle.OracleSet(defs), False, seed=12)
+
+
+def test_batch_bench_workload_sampled():
+    """The batched-documents workload at its benchmark size (50,000 documents, 2.53 GB, seed
+    5: C-like-L exact, C-like-D discard, C-like-B discard, the last refused and hybrid
+    planned), one lex_run_batch with default options (the batch's default lane for this
+    size, 4 KiB).  Every document: token ranges are the exclusive prefix sum of the counts,
+    nothing errs (the generator writes whole tokens), the totals agree.  Sampled documents,
+    the largest of each instance among them, equal their oracle scan element by element."""
+    insts = [(T.CLIKE_L, P.LEX_MODE_EXACT), (T.CLIKE_D, P.LEX_MODE_DISCARD), (T.CLIKE_B, P.LEX_MODE_DISCARD)]
+    buf, offs, sizes, sets = workloads.docs(50000, 5)
+    nd, n = sizes.size, buf.size
+    batch = P.Batch([(P.Lexer.compile(T.as_tuples(d)), m) for d, m in insts])
+    docs = np.zeros(nd, dtype=P.DOC_DTYPE)
+    docs["offset"], docs["length"], docs["inst"] = offs, sizes, sets
+    print(f"[case] batch bench workload: {nd} docs, {n} B, default opts", flush=True)
+    r = batch.run(torch.from_numpy(buf).cuda(), docs, offsets=True)
+    assert r.status == 0 and r.nerrors == 0
+    res = r.docs
+    assert (res["status"] == 0).all() and (res["error_offset"] == sizes).all()
+    cnt = res["ntokens"].astype(np.uint64)
+    want_off = np.zeros(nd, np.uint64)
+    np.cumsum(cnt[:-1], out=want_off[1:])
+    np.testing.assert_array_equal(res["tok_offset"], want_off)
+    assert int(cnt.sum()) == r.ntokens and r.nslices > nd
+    rng = np.random.default_rng(17)
+    pick = set(rng.choice(nd, 300, replace=False).tolist())
+    for k in range(len(insts)):
+        of_k = np.flatnonzero(sets == k)
+        pick.add(int(of_k[np.argmax(sizes[of_k])]))
+    orcs = [oracle.OracleSet(T.as_tuples(d)) for d, _ in insts]
+    for i in sorted(pick):
+        k, a, z = int(sets[i]), int(offs[i]), int(sizes[i])
+        ok, ol, oo, con = orcs[k].lex(bytes(buf[a:a + z]), discard=bool(insts[k][1]), offsets=True)
+        assert con == z, i
+        t0, t1 = int(res["tok_offset"][i]), int(res["tok_offset"][i] + res["ntokens"][i])
+        assert t1 - t0 == ok.size, i
+        np.testing.assert_array_equal(r.kinds[t0:t1].cpu().numpy(), ok, err_msg=f"doc {i}")
+        np.testing.assert_array_equal(r.lens[t0:t1].cpu().numpy().view(np.uint32), ol, err_msg=f"doc {i}")
+        np.testing.assert_array_equal(r.offsets[t0:t1].cpu().numpy(), oo.astype(np.int64), err_msg=f"doc {i}")
