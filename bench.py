@@ -39,6 +39,8 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-documents leg")
     ap.add_argument("--batch-docs", type=int, default=50000)
     ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--batch-only", action="store_true",
+                    help="batched leg without the per-document comparison (for kernel traces)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-framed", action="store_true", help="skip the framed-document leg")
     ap.add_argument("--serve-seconds", type=float, default=4.0, help="per arrival rate (plus 1 s warm-up)")
@@ -225,6 +227,14 @@ def batched_leg(args):
     tot = total.cpu().numpy()
     ntok_batch = int(tot[0])
     per = res.cpu().numpy()[: nd * 32].view(P.DOC_RESULT_DTYPE)
+    head = {
+        "workload": f"{nd} documents, log-normal sizes (median 16 KiB, sigma 1.5, 64 B - 8 MiB), seed 5; "
+                    "C-like-L exact / C-like-D discard / C-like-B discard (refused) = .475/.475/.05",
+        "bytes": n, "tokens": ntok_batch,
+        "batched_gbs": round(n / t_batch / 1e9, 3), "batched_ms": round(t_batch * 1e3, 3),
+    }
+    if args.batch_only:
+        return head
     # one lex_run per document, back to back on the same stream
     cap = int(sizes.max())
     okinds = torch.empty(cap, dtype=torch.uint8, device=dev)
@@ -287,10 +297,7 @@ def batched_leg(args):
         crit = {"critical_doc_bytes": int(sizes[i]), "critical_doc_ms": round(t_crit * 1e3, 3),
                 "critical_doc_mbs": round(int(sizes[i]) / t_crit / 1e6, 1)}
     return {
-        "workload": f"{nd} documents, log-normal sizes (median 16 KiB, sigma 1.5, 64 B - 8 MiB), seed 5; "
-                    "C-like-L exact / C-like-D discard / C-like-B discard (refused) = .475/.475/.05",
-        "bytes": n, "tokens": ntok_batch,
-        "batched_gbs": round(n / t_batch / 1e9, 3), "batched_ms": round(t_batch * 1e3, 3),
+        **head,
         "plain_gbs": round(n / t_plain / 1e9, 3), "plain_ms": round(t_plain * 1e3, 3),
         "speedup": round(t_plain / t_batch, 2),
         "plain_4streams_ms": round(t_plain4 * 1e3, 3), "speedup_vs_4streams": round(t_plain4 / t_batch, 2),

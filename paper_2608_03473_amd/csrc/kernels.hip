@@ -1920,86 +1920,139 @@ __device__ __forceinline__ bool one_lane(const BatchArgs &a, const DocDev &d) {
          (d.length <= a.lane_bytes || (d.flags & 1) || d.inst >= a.ninst || a.inst[d.inst].refused);
 }
 
+__device__ __forceinline__ uint32_t ceil_div(uint32_t x, uint32_t y) { return x / y + (x % y != 0); }
+
 __device__ __forceinline__ uint32_t doc_lanes(const BatchArgs &a, const DocDev &d) {
-  if (spec_split(a, d)) return (uint32_t)(((uint64_t)d.length + a.spec_bytes - 1) / a.spec_bytes);
-  return one_lane(a, d) ? 1 : (uint32_t)(((uint64_t)d.length + a.lane_bytes - 1) / a.lane_bytes);
+  if (spec_split(a, d)) return ceil_div(d.length, a.spec_bytes);
+  return one_lane(a, d) ? 1 : ceil_div(d.length, a.lane_bytes);
 }
 
-// One workgroup: lanes per document, lane numbering (long single-lane documents first),
-// queue reset.
+// The single-workgroup kernels (k_bplan, k_bscan) give each wave a contiguous range of
+// documents and walk it 64 documents at a time, one per lane, so every load is coalesced
+// (one CU serves the whole table: a per-thread range would touch 64 lines per instruction
+// and overflow its L1).  kDocTiles tiles are loaded before any is used.
+constexpr uint32_t kDocTiles = 4;
+
+__device__ __forceinline__ uint64_t wave_sum64(uint64_t v) {
+  for (int k = 32; k; k >>= 1) v += __shfl_xor(v, k);
+  return v;
+}
+
+__device__ __forceinline__ uint64_t wave_incl64(uint64_t v, uint32_t lane) {
+  for (int k = 1; k < 64; k <<= 1) {
+    const uint64_t t = __shfl_up(v, k);
+    if ((int)lane >= k) v += t;
+  }
+  return v;
+}
+
+// Contiguous document range of one wave of a single-workgroup kernel.
+__device__ __forceinline__ void wave_range(uint32_t ndocs, uint32_t &lo, uint32_t &hi) {
+  const uint32_t nw = blockDim.x >> 6, per = (ndocs + nw - 1) / nw;
+  lo = min(ndocs, (threadIdx.x >> 6) * per);
+  hi = min(ndocs, lo + per);
+}
+
+// Sums of three per-wave values over the waves before this one, and over all waves.
+__device__ __forceinline__ void wave_prefix3(const uint64_t (*wpart)[16], uint64_t pre[3], uint64_t tot[3]) {
+  const uint32_t nw = blockDim.x >> 6, me = threadIdx.x >> 6;
+  for (int q = 0; q < 3; ++q) pre[q] = tot[q] = 0;
+  for (uint32_t w = 0; w < nw; ++w)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      pre[q] += w < me ? wpart[q][w] : 0;
+      tot[q] += wpart[q][w];
+    }
+}
+
+// One workgroup: lanes per document, lane numbering (long single-lane documents first, then
+// the rest, each group in document order), speculative-lane numbering, queue reset.  One pass
+// counts, one numbers.
 __global__ void __launch_bounds__(1024) k_bplan(BatchArgs a) {
-  __shared__ uint64_t part[1024];  // 64-bit: a hostile table may ask for more than 2^32 lanes
-  const uint32_t tid = threadIdx.x, nt = blockDim.x;
-  const uint32_t per = (a.ndocs + nt - 1) / nt;
-  const uint32_t lo = min(a.ndocs, tid * per), hi = min(a.ndocs, lo + per);
+  __shared__ uint64_t wpart[3][16];  // 64-bit: a hostile table may ask for more than 2^32 lanes
   __shared__ uint32_t bad;
+  const uint32_t tid = threadIdx.x, lane = tid & 63;
   if (tid == 0) {
     a.meta[kQCount] = 0;
     a.meta[kQEmit] = 0;
     bad = 0;
   }
   __syncthreads();
+  uint32_t lo, hi;
+  wave_range(a.ndocs, lo, hi);
   // the document table is the caller's device data: a document outside the bytes, an
   // unknown instance or flag, or more lanes than the workspace holds stops the batch
-  for (uint32_t d = lo; d < hi; ++d) {
-    const DocDev doc = a.docs[d];
-    if (doc.offset > a.nbytes || doc.length > a.nbytes - doc.offset || doc.inst >= a.ninst || doc.flags > 1)
-      atomicOr(&bad, 1u);
-  }
-  uint64_t base = 0;
-  for (int group = 0; group < 2; ++group) {
-    uint64_t sum = 0;
-    for (uint32_t d = lo; d < hi; ++d) {
-      const DocDev doc = a.docs[d];
-      const uint32_t nl = doc_lanes(a, doc);
-      const bool first = nl == 1 && doc.length > a.lane_bytes;
-      if (group == 0) a.lanes_of[d] = nl;
-      if (first == (group == 0)) sum += nl;
+  uint64_t s_first = 0, s_rest = 0, s_spec = 0;
+  bool my_bad = false;
+  for (uint32_t d0 = lo; d0 < hi; d0 += 64 * kDocTiles) {
+    DocDev doc[kDocTiles];
+#pragma unroll
+    for (uint32_t u = 0; u < kDocTiles; ++u) {
+      const uint32_t d = d0 + u * 64 + lane;
+      doc[u] = d < hi ? a.docs[d] : DocDev{};
     }
-    part[tid] = sum;
-    __syncthreads();
-    for (uint32_t d = 1; d < nt; d <<= 1) {
-      const uint64_t v = tid >= d ? part[tid - d] : 0;
-      __syncthreads();
-      part[tid] += v;
-      __syncthreads();
-    }
-    uint64_t run = base + (tid ? part[tid - 1] : 0);
-    for (uint32_t d = lo; d < hi; ++d) {
-      const uint32_t nl = a.lanes_of[d];
-      const bool first = nl == 1 && a.docs[d].length > a.lane_bytes;
-      if (first == (group == 0)) {
-        a.lane_base[d] = (uint32_t)min<uint64_t>(run, 0xFFFFFFFFu);  // unused when stopped
-        run += nl;
+#pragma unroll
+    for (uint32_t u = 0; u < kDocTiles; ++u) {
+      const uint32_t d = d0 + u * 64 + lane;
+      if (d < hi) {
+        const DocDev &x = doc[u];
+        my_bad |= x.offset > a.nbytes || x.length > a.nbytes - x.offset || x.inst >= a.ninst || x.flags > 1;
+        const uint32_t nl = doc_lanes(a, x);
+        a.lanes_of[d] = nl;
+        a.spec_fail[d] = 0;
+        if (nl == 1 && x.length > a.lane_bytes)
+          s_first += nl;
+        else
+          s_rest += nl;
+        if (spec_split(a, x)) s_spec += nl;
       }
     }
-    base += part[nt - 1];
-    __syncthreads();
   }
-  // speculative lanes: numbered per document, in document order
-  uint64_t sum = 0;
-  for (uint32_t d = lo; d < hi; ++d) {
-    a.spec_fail[d] = 0;
-    if (spec_split(a, a.docs[d])) sum += a.lanes_of[d];
+  if (my_bad) atomicOr(&bad, 1u);
+  s_first = wave_sum64(s_first);
+  s_rest = wave_sum64(s_rest);
+  s_spec = wave_sum64(s_spec);
+  if (lane == 0) {
+    wpart[0][tid >> 6] = s_first;
+    wpart[1][tid >> 6] = s_rest;
+    wpart[2][tid >> 6] = s_spec;
   }
-  part[tid] = sum;
   __syncthreads();
-  for (uint32_t d = 1; d < nt; d <<= 1) {
-    const uint64_t v = tid >= d ? part[tid - d] : 0;
-    __syncthreads();
-    part[tid] += v;
-    __syncthreads();
-  }
-  uint64_t run = tid ? part[tid - 1] : 0;
-  for (uint32_t d = lo; d < hi; ++d) {
-    a.spec_base[d] = (uint32_t)min<uint64_t>(run, 0xFFFFFFFFu);
-    if (spec_split(a, a.docs[d])) run += a.lanes_of[d];
+  uint64_t pre[3], tot[3];
+  wave_prefix3(wpart, pre, tot);
+  uint64_t r_first = pre[0], r_rest = tot[0] + pre[1], r_spec = pre[2];
+  for (uint32_t d0 = lo; d0 < hi; d0 += 64 * kDocTiles) {  // wave-uniform: the scans see every lane
+    DocDev doc[kDocTiles];
+#pragma unroll
+    for (uint32_t u = 0; u < kDocTiles; ++u) {
+      const uint32_t d = d0 + u * 64 + lane;
+      doc[u] = d < hi ? a.docs[d] : DocDev{};
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < kDocTiles; ++u) {
+      const uint32_t d = d0 + u * 64 + lane;
+      const bool in = d < hi;
+      const DocDev &x = doc[u];
+      const uint32_t nl = in ? doc_lanes(a, x) : 0;
+      const bool first = nl == 1 && x.length > a.lane_bytes;
+      const uint64_t vf = first ? nl : 0, vr = first ? 0 : nl, vs = in && spec_split(a, x) ? nl : 0;
+      const uint64_t inf = wave_incl64(vf, lane), inr = wave_incl64(vr, lane), ins = wave_incl64(vs, lane);
+      if (in) {
+        const uint64_t base = first ? r_first + inf - vf : r_rest + inr - vr;
+        a.lane_base[d] = (uint32_t)min<uint64_t>(base, 0xFFFFFFFFu);  // unused when stopped
+        a.spec_base[d] = (uint32_t)min<uint64_t>(r_spec + ins - vs, 0xFFFFFFFFu);
+      }
+      r_first += __shfl(inf, 63);
+      r_rest += __shfl(inr, 63);
+      r_spec += __shfl(ins, 63);
+    }
   }
   if (tid == 0) {
-    const bool stop = bad || base > a.max_lanes || part[nt - 1] > a.max_spec;
+    const uint64_t nlanes = tot[0] + tot[1], nspec = tot[2];
+    const bool stop = bad || nlanes > a.max_lanes || nspec > a.max_spec;
     a.meta[kBad] = stop;
-    a.meta[kNLanes] = stop ? 0 : (uint32_t)base;
-    a.meta[kNSpec] = stop ? 0 : (uint32_t)part[nt - 1];
+    a.meta[kNLanes] = stop ? 0 : (uint32_t)nlanes;
+    a.meta[kNSpec] = stop ? 0 : (uint32_t)nspec;
   }
 }
 
@@ -2372,49 +2425,73 @@ __global__ void __launch_bounds__(1024) k_bscan(BatchArgs a) {
     }
     return;
   }
-  __shared__ uint64_t part[1024];
-  __shared__ uint32_t perr[1024], pnsl[1024];
-  const uint32_t tid = threadIdx.x, nt = blockDim.x;
-  const uint32_t per = (a.ndocs + nt - 1) / nt;
-  const uint32_t lo = min(a.ndocs, tid * per), hi = min(a.ndocs, lo + per);
-  uint64_t sum = 0;
-  uint32_t nerr = 0, nsl = 0;
-  for (uint32_t d = lo; d < hi; ++d) {
-    sum += a.doc_ntok[d];
-    nerr += a.doc_halt[d] != kNone;
-    nsl += a.doc_nsl[d];
+  __shared__ uint64_t wpart[3][16];
+  const uint32_t tid = threadIdx.x, lane = tid & 63;
+  uint32_t lo, hi;
+  wave_range(a.ndocs, lo, hi);
+  uint64_t sum = 0, nerr = 0, nsl = 0;
+  for (uint32_t d0 = lo; d0 < hi; d0 += 64 * kDocTiles) {
+    uint32_t nt_[kDocTiles], h_[kDocTiles], ns_[kDocTiles];
+#pragma unroll
+    for (uint32_t u = 0; u < kDocTiles; ++u) {
+      const uint32_t d = d0 + u * 64 + lane;
+      const bool in = d < hi;
+      nt_[u] = in ? a.doc_ntok[d] : 0;
+      h_[u] = in ? a.doc_halt[d] : kNone;
+      ns_[u] = in ? a.doc_nsl[d] : 0;
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < kDocTiles; ++u) {
+      sum += nt_[u];
+      nerr += h_[u] != kNone;
+      nsl += ns_[u];
+    }
   }
-  part[tid] = sum;
-  perr[tid] = nerr;
-  pnsl[tid] = nsl;
+  sum = wave_sum64(sum);
+  nerr = wave_sum64(nerr);
+  nsl = wave_sum64(nsl);
+  if (lane == 0) {
+    wpart[0][tid >> 6] = sum;
+    wpart[1][tid >> 6] = nerr;
+    wpart[2][tid >> 6] = nsl;
+  }
   __syncthreads();
-  for (uint32_t k = 1; k < nt; k <<= 1) {
-    const uint64_t v = tid >= k ? part[tid - k] : 0;
-    const uint32_t ve = tid >= k ? perr[tid - k] : 0, vn = tid >= k ? pnsl[tid - k] : 0;
-    __syncthreads();
-    part[tid] += v;
-    perr[tid] += ve;
-    pnsl[tid] += vn;
-    __syncthreads();
-  }
-  const uint64_t total = part[nt - 1];
+  uint64_t pre[3], tot[3];
+  wave_prefix3(wpart, pre, tot);
+  const uint64_t total = tot[0];
   const int32_t status = total > a.cap ? -4 : 0;
-  uint64_t run = tid ? part[tid - 1] : 0;
-  for (uint32_t d = lo; d < hi; ++d) {
-    DocResDev r;
-    r.tok_offset = run;
-    r.ntokens = a.doc_ntok[d];
-    r.error_offset = a.docs[d].length;  // a halted document's emit replaces it
-    r.status = status;
-    r.nslices = a.doc_nsl[d];
-    a.res[d] = r;
-    run += r.ntokens;
+  uint64_t run = pre[0];
+  for (uint32_t d0 = lo; d0 < hi; d0 += 64 * kDocTiles) {  // wave-uniform: the scans see every lane
+    uint32_t nt_[kDocTiles], ns_[kDocTiles], len_[kDocTiles];
+#pragma unroll
+    for (uint32_t u = 0; u < kDocTiles; ++u) {
+      const uint32_t d = d0 + u * 64 + lane;
+      const bool in = d < hi;
+      nt_[u] = in ? a.doc_ntok[d] : 0;
+      ns_[u] = in ? a.doc_nsl[d] : 0;
+      len_[u] = in ? a.docs[d].length : 0;
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < kDocTiles; ++u) {
+      const uint32_t d = d0 + u * 64 + lane;
+      const uint64_t incl = wave_incl64(nt_[u], lane);
+      if (d < hi) {
+        DocResDev r;
+        r.tok_offset = run + incl - nt_[u];
+        r.ntokens = nt_[u];
+        r.error_offset = len_[u];  // a halted document's emit replaces it
+        r.status = status;
+        r.nslices = ns_[u];
+        a.res[d] = r;
+      }
+      run += __shfl(incl, 63);
+    }
   }
   if (tid == 0) {
     a.total->ntokens = total;
-    a.total->error_offset = perr[nt - 1];  // documents that did not tokenize completely
+    a.total->error_offset = tot[1];  // documents that did not tokenize completely
     a.total->status = status;
-    a.total->nslices = pnsl[nt - 1];
+    a.total->nslices = (uint32_t)tot[2];
   }
 }
 
