@@ -1818,8 +1818,8 @@ __global__ void k_onepass_reset(uint64_t *st, uint32_t n, uint32_t *ctr) {
 // slice, error offset relative to the document.
 //
 // Hybrid plan for refused token sets: a document of such a set (no useful certified byte),
-// not flagged serial and longer than one speculative lane (kSpecLane bytes, or lane_bytes if
-// larger) is split speculatively.  Lane k starts at k * S in the start row as if a token
+// not flagged serial and longer than one speculative lane (kSpecX bytes) is split
+// speculatively.  Lane k starts at k * S in the start row as if a token
 // began there, walks its range and kSpecX bytes on, and restarts one byte further on after
 // a halt, recording the token starts of its first kSpecX bytes (head) and of the kSpecX
 // bytes after its range (tail).  Lane 0 is the serial scan.  If lane k - 1's walk is the
@@ -1834,8 +1834,7 @@ __global__ void k_onepass_reset(uint64_t *st, uint32_t n, uint32_t *ctr) {
 // its own cut (the serial scan halts there: the one-lane scan then reports the error as
 // usual).
 constexpr int kMaxInst = 8;
-constexpr uint32_t kSpecLane = kHybridLane;
-constexpr uint32_t kSpecX = 2048;  // at most kSpecLane
+constexpr uint32_t kSpecX = 2048;  // the sync window; at most the speculative lane
 constexpr uint32_t kSpecWords = kSpecX / 32;
 
 struct BatchInst {
@@ -2853,11 +2852,16 @@ hipError_t run_pipeline(const DevTable &t, const CertMap &cm, const uint8_t *in,
 }
 
 // ------------------------------------------------------------------ batches
-static uint32_t batch_max_lanes(uint32_t ndocs, uint64_t nbytes, uint32_t lane_bytes) {
-  return (uint32_t)std::min<uint64_t>(0xFFFFFFF0ull, (uint64_t)ndocs + nbytes / lane_bytes + 1);
-}
+// A batch's speculative lane is kSpecX bytes, the shortest the sync window allows: the
+// speculative walks ([k S, (k + 1) S + kSpecX)) are serial and few (refused documents
+// only), so their length, not their number, sets the walk kernel's time.
+static uint32_t batch_spec_bytes(uint32_t) { return kSpecX; }
 
-static uint32_t batch_spec_bytes(uint32_t lane_bytes) { return std::max(kSpecLane, lane_bytes); }
+// a document of n bytes has ceil(n / L) <= n / L + 1 lanes, L its lane length
+static uint32_t batch_max_lanes(uint32_t ndocs, uint64_t nbytes, uint32_t lane_bytes) {
+  const uint32_t shortest = std::min(lane_bytes, batch_spec_bytes(lane_bytes));
+  return (uint32_t)std::min<uint64_t>(0xFFFFFFF0ull, (uint64_t)ndocs + nbytes / shortest + 1);
+}
 
 // speculative lanes: a split document of n bytes has ceil(n / S) <= n / S + 1 of them
 static uint32_t batch_max_spec(uint32_t ndocs, uint64_t nbytes, uint32_t lane_bytes) {

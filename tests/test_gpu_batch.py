@@ -162,8 +162,11 @@ def test_batch_graph_replays(setup):
         _ = batch.run(dev, docs)  # eager work between replays
 
 
+SPEC_LANE = 2048  # a batch's speculative lane: the sync window, the shortest it allows
+
+
 def test_batch_refused_hybrid_plan(setup):
-    """Documents of the refused set C-like-B longer than one speculative lane (4 KiB) are
+    """Documents of the refused set C-like-B longer than one speculative lane (2 KiB) are
     split by the hybrid plan: each must still equal the oracle's serial scan, split clean
     documents report many slices, and those that must fall back (the serial scan halts; a
     block comment longer than the sync window across a lane boundary; a serial flag) run as
@@ -198,5 +201,6 @@ def test_batch_refused_hybrid_plan(setup):
     ns = r.docs["nslices"]
     assert all(ns[i] > 1 for i in range(1, 6)), ns  # clean and longer than one lane: split
     assert ns[7] == 1 and ns[8] == 1, ns            # the long comment and the serial flag: one slice
-    assert ns[9] == 2, ns                            # the last lane empty: the previous one takes the rest
+    # the last lane empty: the previous one takes the rest (lanes of SPEC_LANE bytes)
+    assert ns[9] == -(-8400 // SPEC_LANE) - 1, ns
     assert ns[5] >= 3000000 // 4096 // 2
