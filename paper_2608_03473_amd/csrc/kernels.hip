@@ -1909,27 +1909,38 @@ __device__ __forceinline__ BatchLds batch_stage(const BatchArgs &a) {
   return BatchLds{lds_bytes_of(smem), info, kind, luts, smem + batch_lds_offset(a.nrows, a.ninst)};
 }
 
-__device__ __forceinline__ bool spec_split(const BatchArgs &a, const DocDev &d) {
-  return d.inst < a.ninst && a.inst[d.inst].refused && !(d.flags & 1) && d.length > a.spec_bytes;
+// Bit k: instance k's set is refused.  Built from uniform loads, so the per-document tests
+// below index no kernel argument by a per-lane value (that compiles to a dependent vector
+// load from argument memory).
+__device__ __forceinline__ uint32_t refused_mask(const BatchArgs &a) {
+  uint32_t m = 0;
+  for (uint32_t k = 0; k < a.ninst; ++k) m |= (a.inst[k].refused ? 1u : 0u) << k;
+  return m;
 }
 
-__device__ __forceinline__ bool one_lane(const BatchArgs &a, const DocDev &d) {
-  // (an unknown instance stops the batch; it is never looked up)
-  return !spec_split(a, d) &&
-         (d.length <= a.lane_bytes || (d.flags & 1) || d.inst >= a.ninst || a.inst[d.inst].refused);
+__device__ __forceinline__ bool spec_split(const BatchArgs &a, uint32_t rm, const DocDev &d) {
+  return d.inst < a.ninst && ((rm >> d.inst) & 1) && !(d.flags & 1) && d.length > a.spec_bytes;
+}
+
+__device__ __forceinline__ bool one_lane(const BatchArgs &a, uint32_t rm, const DocDev &d) {
+  // (an unknown instance stops the batch)
+  return !spec_split(a, rm, d) &&
+         (d.length <= a.lane_bytes || (d.flags & 1) || d.inst >= a.ninst || ((rm >> d.inst) & 1));
 }
 
 __device__ __forceinline__ uint32_t ceil_div(uint32_t x, uint32_t y) { return x / y + (x % y != 0); }
 
-__device__ __forceinline__ uint32_t doc_lanes(const BatchArgs &a, const DocDev &d) {
-  if (spec_split(a, d)) return ceil_div(d.length, a.spec_bytes);
-  return one_lane(a, d) ? 1 : ceil_div(d.length, a.lane_bytes);
+__device__ __forceinline__ uint32_t doc_lanes(const BatchArgs &a, uint32_t rm, const DocDev &d) {
+  if (spec_split(a, rm, d)) return ceil_div(d.length, a.spec_bytes);
+  return one_lane(a, rm, d) ? 1 : ceil_div(d.length, a.lane_bytes);
 }
 
 // The single-workgroup kernels (k_bplan, k_bscan) give each wave a contiguous range of
 // documents and walk it 64 documents at a time, one per lane, so every load is coalesced
 // (one CU serves the whole table: a per-thread range would touch 64 lines per instruction
-// and overflow its L1).  kDocTiles tiles are loaded before any is used.
+// and overflow its L1).  kDocTiles tiles are loaded before any is used, unconditionally from
+// an index clamped into the range (a guarded load compiles to a branch that waits on it);
+// lanes past the range then drop what they loaded.
 constexpr uint32_t kDocTiles = 4;
 
 __device__ __forceinline__ uint64_t wave_sum64(uint64_t v) {
@@ -1971,6 +1982,7 @@ __global__ void __launch_bounds__(1024) k_bplan(BatchArgs a) {
   __shared__ uint64_t wpart[3][16];  // 64-bit: a hostile table may ask for more than 2^32 lanes
   __shared__ uint32_t bad;
   const uint32_t tid = threadIdx.x, lane = tid & 63;
+  const uint32_t rm = refused_mask(a);
   if (tid == 0) {
     a.meta[kQCount] = 0;
     a.meta[kQEmit] = 0;
@@ -1986,24 +1998,21 @@ __global__ void __launch_bounds__(1024) k_bplan(BatchArgs a) {
   for (uint32_t d0 = lo; d0 < hi; d0 += 64 * kDocTiles) {
     DocDev doc[kDocTiles];
 #pragma unroll
-    for (uint32_t u = 0; u < kDocTiles; ++u) {
-      const uint32_t d = d0 + u * 64 + lane;
-      doc[u] = d < hi ? a.docs[d] : DocDev{};
-    }
+    for (uint32_t u = 0; u < kDocTiles; ++u) doc[u] = a.docs[min(d0 + u * 64 + lane, hi - 1)];
 #pragma unroll
     for (uint32_t u = 0; u < kDocTiles; ++u) {
       const uint32_t d = d0 + u * 64 + lane;
       if (d < hi) {
         const DocDev &x = doc[u];
         my_bad |= x.offset > a.nbytes || x.length > a.nbytes - x.offset || x.inst >= a.ninst || x.flags > 1;
-        const uint32_t nl = doc_lanes(a, x);
+        const uint32_t nl = doc_lanes(a, rm, x);
         a.lanes_of[d] = nl;
         a.spec_fail[d] = 0;
         if (nl == 1 && x.length > a.lane_bytes)
           s_first += nl;
         else
           s_rest += nl;
-        if (spec_split(a, x)) s_spec += nl;
+        if (spec_split(a, rm, x)) s_spec += nl;
       }
     }
   }
@@ -2023,18 +2032,15 @@ __global__ void __launch_bounds__(1024) k_bplan(BatchArgs a) {
   for (uint32_t d0 = lo; d0 < hi; d0 += 64 * kDocTiles) {  // wave-uniform: the scans see every lane
     DocDev doc[kDocTiles];
 #pragma unroll
-    for (uint32_t u = 0; u < kDocTiles; ++u) {
-      const uint32_t d = d0 + u * 64 + lane;
-      doc[u] = d < hi ? a.docs[d] : DocDev{};
-    }
+    for (uint32_t u = 0; u < kDocTiles; ++u) doc[u] = a.docs[min(d0 + u * 64 + lane, hi - 1)];
 #pragma unroll
     for (uint32_t u = 0; u < kDocTiles; ++u) {
       const uint32_t d = d0 + u * 64 + lane;
       const bool in = d < hi;
       const DocDev &x = doc[u];
-      const uint32_t nl = in ? doc_lanes(a, x) : 0;
+      const uint32_t nl = in ? doc_lanes(a, rm, x) : 0;
       const bool first = nl == 1 && x.length > a.lane_bytes;
-      const uint64_t vf = first ? nl : 0, vr = first ? 0 : nl, vs = in && spec_split(a, x) ? nl : 0;
+      const uint64_t vf = first ? nl : 0, vr = first ? 0 : nl, vs = in && spec_split(a, rm, x) ? nl : 0;
       const uint64_t inf = wave_incl64(vf, lane), inr = wave_incl64(vr, lane), ins = wave_incl64(vs, lane);
       if (in) {
         const uint64_t base = first ? r_first + inf - vf : r_rest + inr - vr;
@@ -2063,7 +2069,7 @@ __global__ void __launch_bounds__(256) k_bmap(BatchArgs a) {
   for (uint32_t d = wave; d < a.ndocs; d += nwaves) {
     const uint32_t lb = a.lane_base[d], nl = a.lanes_of[d];
     for (uint32_t k = lane; k < nl; k += 64) a.lane_doc[lb + k] = d;
-    if (spec_split(a, a.docs[d]))
+    if (spec_split(a, refused_mask(a), a.docs[d]))
       for (uint32_t k = lane; k < nl; k += 64) a.spec_doc[a.spec_base[d] + k] = d;
   }
 }
@@ -2329,7 +2335,7 @@ __global__ void __launch_bounds__(256) k_bcount(BatchArgs a) {
     const BatchInst &in = a.inst[valid ? doc.inst : 0];
     const uint8_t *src = a.bytes + doc.offset;
     const uint8_t *lut = l.luts + 256 * (valid ? doc.inst : 0);
-    const bool spec = valid && spec_split(a, doc);
+    const bool spec = valid && spec_split(a, refused_mask(a), doc);
     if (valid && !spec) {
       if (jj == 0) start = 0;
       else start = search_cert(src, doc.length, in.ca, lut, jj * a.lane_bytes, a.lane_bytes, kNone);
@@ -2433,12 +2439,18 @@ __global__ void __launch_bounds__(1024) k_bscan(BatchArgs a) {
     uint32_t nt_[kDocTiles], h_[kDocTiles], ns_[kDocTiles];
 #pragma unroll
     for (uint32_t u = 0; u < kDocTiles; ++u) {
-      const uint32_t d = d0 + u * 64 + lane;
-      const bool in = d < hi;
-      nt_[u] = in ? a.doc_ntok[d] : 0;
-      h_[u] = in ? a.doc_halt[d] : kNone;
-      ns_[u] = in ? a.doc_nsl[d] : 0;
+      const uint32_t dc = min(d0 + u * 64 + lane, hi - 1);
+      nt_[u] = a.doc_ntok[dc];
+      h_[u] = a.doc_halt[dc];
+      ns_[u] = a.doc_nsl[dc];
     }
+#pragma unroll
+    for (uint32_t u = 0; u < kDocTiles; ++u)
+      if (d0 + u * 64 + lane >= hi) {
+        nt_[u] = 0;
+        h_[u] = kNone;
+        ns_[u] = 0;
+      }
 #pragma unroll
     for (uint32_t u = 0; u < kDocTiles; ++u) {
       sum += nt_[u];
@@ -2464,12 +2476,14 @@ __global__ void __launch_bounds__(1024) k_bscan(BatchArgs a) {
     uint32_t nt_[kDocTiles], ns_[kDocTiles], len_[kDocTiles];
 #pragma unroll
     for (uint32_t u = 0; u < kDocTiles; ++u) {
-      const uint32_t d = d0 + u * 64 + lane;
-      const bool in = d < hi;
-      nt_[u] = in ? a.doc_ntok[d] : 0;
-      ns_[u] = in ? a.doc_nsl[d] : 0;
-      len_[u] = in ? a.docs[d].length : 0;
+      const uint32_t dc = min(d0 + u * 64 + lane, hi - 1);
+      nt_[u] = a.doc_ntok[dc];
+      ns_[u] = a.doc_nsl[dc];
+      len_[u] = a.docs[dc].length;
     }
+#pragma unroll
+    for (uint32_t u = 0; u < kDocTiles; ++u)
+      if (d0 + u * 64 + lane >= hi) nt_[u] = 0;  // the scan adds nothing past the range
 #pragma unroll
     for (uint32_t u = 0; u < kDocTiles; ++u) {
       const uint32_t d = d0 + u * 64 + lane;
