@@ -120,6 +120,13 @@ def doc_plan(count: int, seed: int, median=16384, sigma=1.5, lo=64, hi=8 << 20):
     return sizes, sets
 
 
+def doc(seed: int, i: int, size: int, set_id: int) -> np.ndarray:
+    """Document i of the batched workload alone (the bytes docs() places at its offset)."""
+    buf = np.empty(int(size), np.uint8)
+    _load().wl_clike(buf.ctypes.data, int(size), substream(seed, 1000 + i), 1 if set_id == DOC_B else 0, 0)
+    return buf
+
+
 def docs(count: int, seed: int, **kw):
     """Concatenated documents of the batched workload.
     Returns (bytes u8[total], offsets u64[count], sizes u64[count], set_ids u8[count])."""
