@@ -19,6 +19,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+MANIFEST_DIR = os.path.join(ROOT, "tests", "golden")  # the oracle's whole-stream digests
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2608_03473_amd", "csrc", "kernels.hip")
 HBM_SUMMARY = os.path.join(ROOT, "profiles", "onepass_clike512_hbm.md")
 
@@ -44,6 +45,10 @@ def parse():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-framed", action="store_true", help="skip the framed-document leg")
     ap.add_argument("--serve-seconds", type=float, default=4.0, help="per arrival rate (plus 1 s warm-up)")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the 1 MiB, 256 MiB JSON and stray-byte configuration legs")
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="threads of the chunked CPU baseline's all-cores figure (0: the cores this process may use)")
     ap.add_argument("--copy-ref", action="store_true",
                     help="also run one plain device copy of n bytes (scale for HBM counters)")
     return ap.parse_args()
@@ -120,6 +125,7 @@ def main():
     if status != 0 or err != n:
         print(f"bench: scan failed status={status} error_offset={err} n={n}", file=sys.stderr)
         sys.exit(1)
+    parity = stream_parity("clike_512mib", n, args.seed, args.chunk_bytes, ntok, err, kinds, lens)
     phases = np.array([e.elapsed_ms() for e in evs])  # steps x 4
     ph_mean = phases.mean(axis=0)
     plan = lx.plan(n, mode, opts)
@@ -157,6 +163,7 @@ def main():
         },
         "tokens_per_s": round(ntok / (ms * 1e-3), 1),
         "path_roofline_frac": round(path_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "parity": parity,
         "phase_ms": {k: round(float(v), 4) for k, v in zip(names, ph_mean)},
         "roofline": {
             "bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
@@ -168,6 +175,8 @@ def main():
         },
         "cpu_baseline": None,
     }
+    if not args.no_configs:
+        out["configs"] = configs_leg(args, host, lx, kinds, lens, res)
     if not args.no_batched:
         del data, kinds, lens, ws
         torch.cuda.empty_cache()
@@ -180,7 +189,156 @@ def main():
         out["serving"] = serving_leg(args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(host, args)
+        out["cpu_chunked"] = cpu_chunked_leg(host, lx, args)
     print(json.dumps(out), flush=True)
+
+
+def manifest_case(name):
+    """The oracle's recorded digests for a benchmark case (tests/golden/stream_manifest.json,
+    written from the oracle alone), or None."""
+    try:
+        with open(os.path.join(MANIFEST_DIR, "stream_manifest.json")) as f:
+            return json.load(f)["cases"].get(name)
+    except OSError:
+        return None
+
+
+def _digests(kinds_np, lens_np):
+    sys.path.insert(0, MANIFEST_DIR)
+    import stream_manifest as SM
+    return SM.sha(kinds_np), SM.sha(lens_np.astype("<u4", copy=False))
+
+
+def stream_parity(name, n, seed, chunk_bytes, ntok, err, kinds, lens):
+    """Whole-stream parity of the last timed scan against the oracle's digests: token count,
+    error offset, and the SHA-256 of every kind and every length.  None when the run is not
+    the recorded workload."""
+    case = manifest_case(name)
+    if case is None or case.get("n") != n or case.get("seed") != seed or chunk_bytes <= 0:
+        return None
+    if ntok != case["ntokens"] or err != case["error_offset"]:
+        return False
+    k = kinds[:ntok].cpu().numpy()
+    l = lens[:ntok].cpu().numpy().view("<u4")
+    dk, dl = _digests(k, l)
+    return dk == case["kinds"] and dl == case["lens"]
+
+
+def timed_scan(lx, data, n, mode, kinds, lens, res, ws, opts, steps, warmup):
+    """warmup untimed scans, then `steps` scans bracketed by synchronisations; ms per scan."""
+    import torch
+
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        lx.run_into(data, n, mode, kinds, lens, None, n, res, ws, opts, stream)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        lx.run_into(data, n, mode, kinds, lens, None, n, res, ws, opts, stream)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t) * 1e3 / steps
+
+
+def configs_leg(args, host512, lx_l, kinds, lens, res):
+    """The other single-buffer configurations, same protocol as the headline (input in HBM,
+    outputs and workspace preallocated, warm-up then timed steps): the 1 MiB C-like corpus
+    (seed 1, exact), the 512 MiB corpus with the stray 0x01 byte the oracle's rule picked
+    (seed 3; the scan halts there, Corollary 1), and the 256 MiB JSON corpus in modulo-I
+    mode (seed 4).  Each reports input GB/s, tokens/s, (N + 5 T_out) / t against 8 TB/s,
+    the error offset and whole-stream parity with the oracle's digests."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from workloads import tokensets as T
+    import paper_2608_03473_amd as P
+
+    dev = torch.device("cuda", 0)
+    out = {}
+
+    def leg(key, case_name, lx, buf, mode, steps, what):
+        n = buf.size
+        data = torch.from_numpy(buf).to(dev)
+        opts = P.RunOpts(chunk_bytes=64 << 10)
+        ws = torch.empty(lx.workspace_size(n, mode, opts), dtype=torch.uint8, device=dev)
+        ms = timed_scan(lx, data, n, mode, kinds, lens, res, ws, opts, steps, args.warmup)
+        r = res.cpu().numpy()
+        ntok, err = int(r[0]), int(r[1])
+        plan = lx.plan(n, mode, opts)
+        case = manifest_case(case_name)
+        par = None
+        if case is not None:
+            par = ntok == case["ntokens"] and err == case["error_offset"]
+            if par:
+                dk, dl = _digests(kinds[:ntok].cpu().numpy(), lens[:ntok].cpu().numpy().view("<u4"))
+                par = dk == case["kinds"] and dl == case["lens"]
+        out[key] = {
+            "workload": what, "n_bytes": n, "ms": round(ms, 4), "steps": steps,
+            "gbs": round(n / (ms * 1e-3) / 1e9, 3), "tokens": ntok, "tokens_per_s": round(ntok / (ms * 1e-3), 1),
+            "roofline_frac": round((n + 5 * ntok) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "error_offset": err, "slices": int((int(r[2]) >> 32) & 0xFFFFFFFF),
+            "path": plan["path"], "lane_bytes": plan["lane_bytes"], "parity": par,
+        }
+        log(args, f"config {key}: {out[key]}")
+        del data, ws
+
+    leg("config1_1mib", "clike_1mib", lx_l, workloads.clike(1 << 20, 1), P.LEX_MODE_EXACT, 200,
+        "C-like-L exact mode, 1 MiB C-like corpus (seed 1), 64 KiB chunks (launch-bound)")
+    stray = manifest_case("clike_512mib_stray_error")
+    if stray is not None and host512.size == stray["n"] and args.seed == stray["seed"]:
+        bad = np.array(host512, copy=True)
+        bad[stray["stray_offset"]] = 1
+        leg("config2_stray", "clike_512mib_stray_error", lx_l, bad, P.LEX_MODE_EXACT, args.steps,
+            f"C-like-L exact mode, 512 MiB corpus (seed 2) with 0x01 at offset {stray['stray_offset']} "
+            f"(seed 3, draw {stray['stray_draw']})")
+        del bad
+    lx_j = P.Lexer.compile(T.as_tuples(T.JSON))
+    leg("config3_json", "json_256mib", lx_j, workloads.json(256 << 20, 4), P.LEX_MODE_DISCARD, args.steps,
+        "JSON discard mode (WS deleted), 256 MiB pretty-printed JSON corpus (seed 4), 64 KiB chunks")
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_chunked_leg(host, lx, args):
+    """The multithreaded chunked CPU lexer (lex_cpu_chunked, the paper's executor: 64 KiB
+    equal-division chunks cut at certified bytes, threads taking chunks from a counter,
+    ordered concatenation) over the library's packed table, on the same corpus in host
+    memory: median of 5 passes at 1 thread, 8 threads and every core this process may use
+    (no affinity mask).  A baseline for context, never a fallback of the GPU path."""
+    import numpy as np
+
+    n = host.size
+    kinds = np.empty(n, np.uint8)
+    lens = np.empty(n, np.uint32)
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    share = int(os.environ.get("OMP_NUM_THREADS", avail) or avail)
+    allc = args.cpu_threads or max(1, min(avail, share))
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
+    case = manifest_case("clike_512mib")
+    out = {"kind": "multithreaded chunked lexer (lex_cpu_chunked)", "unit": "GB/s", "cpu_model": model,
+           "nproc": os.cpu_count(), "cores_available": avail, "affinity_mask": False, "chunk_bytes": 64 << 10,
+           "sample": f"the whole {n} B corpus in host memory, median of 5 passes"}
+    for label, th in (("threads_1", 1), ("threads_8", 8), ("threads_all", allc)):
+        ts = []
+        for _ in range(5):
+            t = time.perf_counter()
+            k, l, nt, err, nch = lx.cpu_chunked(host, 0, chunk_bytes=64 << 10, threads=th, kinds=kinds, lens=lens)
+            ts.append(time.perf_counter() - t)
+        med = float(np.median(ts))
+        par = None
+        if case is not None and n == case["n"]:
+            dk, dl = _digests(k, l)
+            par = nt == case["ntokens"] and err == case["error_offset"] and dk == case["kinds"] and dl == case["lens"]
+        out[label] = {"threads": th, "value": round(n / med / 1e9, 4), "ms": round(med * 1e3, 2),
+                      "chunks": nch, "parity": par}
+        log(args, f"cpu chunked {label}: {out[label]}")
+    out["speedup_all_vs_1"] = round(out["threads_all"]["value"] / out["threads_1"]["value"], 2)
+    return out
 
 
 def batched_leg(args):
@@ -227,11 +385,46 @@ def batched_leg(args):
     tot = total.cpu().numpy()
     ntok_batch = int(tot[0])
     per = res.cpu().numpy()[: nd * 32].view(P.DOC_RESULT_DTYPE)
+    # parity of every document with the oracle's digests (counts, error offsets, tokens)
+    case = manifest_case("docs_50k")
+    par = None
+    if case is not None and nd == case["count"]:
+        sys.path.insert(0, MANIFEST_DIR)
+        import stream_manifest as SM
+        par = (SM.sha(per["ntokens"].astype("<u8")) == case["ntokens"]
+               and SM.sha(per["error_offset"].astype("<u8")) == case["error_offsets"]
+               and ntok_batch == case["total_tokens"])
+        if par:
+            dk, dl = _digests(kinds[:ntok_batch].cpu().numpy(), lens[:ntok_batch].cpu().numpy().view("<u4"))
+            par = dk == case["kinds"] and dl == case["lens"]
+    # the same launch sequence captured once in a hipGraph and replayed
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream(device=dev)
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            batch.run_into(data, n, docs_dev, nd, kinds, lens, None, n, res, total, ws,
+                           stream=torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    for _ in range(2):
+        g.replay()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(args.batch_steps):
+        g.replay()
+    torch.cuda.synchronize()
+    t_graph = (time.perf_counter() - t) / args.batch_steps
+    graph_same = int(total.cpu().numpy()[0]) == ntok_batch
+    del g
     head = {
         "workload": f"{nd} documents, log-normal sizes (median 16 KiB, sigma 1.5, 64 B - 8 MiB), seed 5; "
                     "C-like-L exact / C-like-D discard / C-like-B discard (refused) = .475/.475/.05",
         "bytes": n, "tokens": ntok_batch,
         "batched_gbs": round(n / t_batch / 1e9, 3), "batched_ms": round(t_batch * 1e3, 3),
+        "batched_graph_gbs": round(n / t_graph / 1e9, 3), "batched_graph_ms": round(t_graph * 1e3, 3),
+        "graph_same_tokens": graph_same,
+        "roofline_frac": round((n + 5 * ntok_batch) / min(t_batch, t_graph) / 1e9 / HBM_PEAK_GBS, 4),
+        "parity": par,
     }
     if args.batch_only:
         return head
@@ -364,11 +557,15 @@ def serving_leg(args):
 
     pool = serve.make_pool(2048, 7)
     server = serve.Server(serve.instances(), budget_bytes=16 << 30, slots=4)
-    out = []
+    out = {"seconds_per_rate": args.serve_seconds, "warmup_seconds": 1.0, "pool": "3 x 2048 documents",
+           "deviation": "the configuration asks 60 s per rate; this bench runs --serve-seconds per rate to keep "
+                        "the driver's run within minutes (the 60 s run: python -m paper_2608_03473_amd.serve "
+                        "--seconds 60 --warmup 2 --pool 16384)",
+           "rates": []}
     for rate in (2000.0, 10000.0, 50000.0):
         m = serve.open_loop(server, pool, rate, args.serve_seconds + 1.0, 6, warmup=1.0)
         log(args, f"serving {rate:.0f}/s: {m}")
-        out.append(m)
+        out["rates"].append(m)
     return out
 
 

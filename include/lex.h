@@ -251,6 +251,25 @@ int lex_run_batch(const lex_batch *batch, const uint8_t *d_bytes, uint64_t nbyte
                   lex_doc_result *d_res, lex_result *d_total, void *d_ws, size_t ws_bytes,
                   const lex_run_opts *opts, void *stream);
 
+/* ---- Host baseline (not a GPU path, and never called by one).
+ *
+ * The paper's CPU executor (Section 6) on the host's cores, for timing the GPU scans
+ * against: an equal-division plan cuts bytes[0, n) (host memory) before the first useful
+ * certified byte of `mode` at or after each multiple of chunk_bytes (0 = 64 KiB; none in
+ * LEX_MODE_SERIAL or when the useful map is empty); nthreads worker threads (0 = one per
+ * hardware thread) take the chunks from a shared counter and scan each one alone with
+ * the longest-match loop of Section 3 over this lexer's packed table; the per-chunk
+ * streams are concatenated in order up to the first chunk that halts (Corollary 1).  By
+ * Theorem 1 and Theorem 3 the result is the serial scan's, exactly as lex_run's.
+ * kinds and lens are host arrays of cap >= n entries (chunks stage their tokens at their
+ * own byte offsets before the concatenation compacts them); *result (host) receives the
+ * token count, con(w) as error_offset, LEX_OK and the number of chunks as nslices.  Runs
+ * synchronously; returns LEX_EINVAL on bad arguments (cap < n included), LEX_ELIMIT for
+ * n > 2^32 - 16.  Failed lookahead is not bounded here (plain re-scans from the last
+ * accepting position). */
+int lex_cpu_chunked(const lex_dfa *dfa, const uint8_t *bytes, uint64_t n, int mode, uint8_t *kinds, uint32_t *lens,
+                    uint64_t cap, uint64_t chunk_bytes, uint32_t nthreads, lex_result *result);
+
 /* Certificate bitmap of step (a) on its own (device pointers): d_bits[i >> 6] bit (i & 63)
  * is set iff byte d_bytes[i] is in the useful map of `mode`; ceil(n / 64) u64 words. */
 int lex_cert_bitmap(const lex_dfa *dfa, const uint8_t *d_bytes, uint64_t n, int mode, uint64_t *d_bits,

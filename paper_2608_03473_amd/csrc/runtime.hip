@@ -356,24 +356,30 @@ int lex_plan(const lex_dfa *d, uint64_t n, int mode, const lex_run_opts *opts, l
   return LEX_OK;
 }
 
-int lex_run(const lex_dfa *d, const uint8_t *d_bytes, uint64_t n, int mode, uint8_t *d_kinds, uint32_t *d_lens,
-            uint64_t *d_offsets, uint64_t cap, lex_result *d_result, void *d_ws, size_t ws_bytes,
-            const lex_run_opts *opts, void *stream) {
-  if (!d || !d_result || (!d_bytes && n) || !d_ws) return LEX_EINVAL;
+}  // extern "C"
+
+namespace {
+
+// Argument checks of a scan (host only).
+int check_scan_args(const lex_dfa *d, const uint8_t *d_bytes, uint64_t n, uint8_t *d_kinds, uint32_t *d_lens,
+                    uint64_t cap, lex_result *d_result) {
+  if (!d || !d_result || (!d_bytes && n)) return LEX_EINVAL;
   if (cap && (!d_kinds || !d_lens)) return LEX_EINVAL;
   // outputs leave the kernels in 16-byte chunks
   if ((reinterpret_cast<uintptr_t>(d_kinds) | reinterpret_cast<uintptr_t>(d_lens)) & 15) return LEX_EINVAL;
   if (n > 0xFFFFFFF0ull) return LEX_ELIMIT;
-  Resolved r;
-  int rc = resolve(d, n, mode, opts, r);
-  if (rc != LEX_OK) return rc;
+  return LEX_OK;
+}
+
+// Carves the workspace and enqueues one scan on the device copy dc of d's tables.
+int enqueue_scan(const lex_dfa *d, DevCopy *dc, const Resolved &r, const uint8_t *d_bytes, uint64_t n,
+                 uint8_t *d_kinds, uint32_t *d_lens, uint64_t *d_offsets, uint64_t cap, lex_result *d_result,
+                 void *d_ws, size_t ws_bytes, const lex_run_opts *opts, void *stream) {
   lexk::Plan p;
   if (!lexk::carve(d_ws, ws_bytes, (uint32_t)n, r.lane_bytes, r.block, r.path == 1 && !r.hybrid, r.windowed, r.hybrid,
                    p))
     return LEX_ELIMIT;
   const int m = r.table;
-  DevCopy *dc = device_copy(const_cast<lex_dfa *>(d));
-  if (!dc) return LEX_EDEVICE;
   lexk::DevTable t{dc->d_table[m], dc->d_rowinfo[m], dc->d_rowkind, d->c.nrows, d->c.row_sink, d->c.row_fail,
                    d->c.monotone ? 1 : 0, d->all_counted[m] ? 1 : 0};
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -388,6 +394,28 @@ int lex_run(const lex_dfa *d, const uint8_t *d_bytes, uint64_t n, int mode, uint
                                                d_lens, d_offsets, cap, res, s, ev);
   return e == hipSuccess ? LEX_OK : LEX_EDEVICE;
 }
+
+}  // namespace
+
+// The host tables of a compiled lexer, for the host-side chunked baseline (cpu_chunked.cc).
+const lexc::Compiled &lex_compiled(const lex_dfa *d) { return d->c; }
+
+extern "C" {
+
+int lex_run(const lex_dfa *d, const uint8_t *d_bytes, uint64_t n, int mode, uint8_t *d_kinds, uint32_t *d_lens,
+            uint64_t *d_offsets, uint64_t cap, lex_result *d_result, void *d_ws, size_t ws_bytes,
+            const lex_run_opts *opts, void *stream) {
+  int rc = check_scan_args(d, d_bytes, n, d_kinds, d_lens, cap, d_result);
+  if (rc != LEX_OK) return rc;
+  if (!d_ws) return LEX_EINVAL;
+  Resolved r;
+  rc = resolve(d, n, mode, opts, r);
+  if (rc != LEX_OK) return rc;
+  DevCopy *dc = device_copy(const_cast<lex_dfa *>(d));
+  if (!dc) return LEX_EDEVICE;
+  return enqueue_scan(d, dc, r, d_bytes, n, d_kinds, d_lens, d_offsets, cap, d_result, d_ws, ws_bytes, opts, stream);
+}
+
 
 int lex_batch_create(const lex_dfa *const *dfas, const int32_t *modes, uint32_t ninst, lex_batch **out, char *err,
                      size_t errlen) {

@@ -188,6 +188,27 @@ class Lexer:
         k = min(ntok, cap) if status == 0 else 0
         return RunResult(kinds[:k], lens[:k], offs[:k] if offs is not None else None, ntok, err, status, nsl)
 
+    def cpu_chunked(self, data, mode: int = abi.LEX_MODE_EXACT, chunk_bytes: int = 64 << 10, threads: int = 0,
+                    kinds=None, lens=None):
+        """The host baseline (lex_cpu_chunked): the paper's multithreaded chunked executor
+        on the CPU cores over this lexer's tables.  data: a uint8 numpy array; kinds/lens:
+        optional preallocated numpy outputs of at least data.size entries.  Returns
+        (kinds, lens, ntokens, error_offset, nchunks); kinds/lens are views of length
+        ntokens.  Not a GPU path."""
+        w = np.ascontiguousarray(data, dtype=np.uint8)
+        n = w.size
+        if kinds is None:
+            kinds = np.empty(max(n, 1), np.uint8)
+        if lens is None:
+            lens = np.empty(max(n, 1), np.uint32)
+        assert kinds.dtype == np.uint8 and lens.dtype == np.uint32
+        r = abi.Result()
+        abi.check(abi.lib().lex_cpu_chunked(self._h, w.ctypes.data if n else None, n, mode, kinds.ctypes.data,
+                                            lens.ctypes.data, min(kinds.size, lens.size) if n else 0,
+                                            chunk_bytes, threads, C.byref(r)), "lex_cpu_chunked")
+        k = r.ntokens
+        return kinds[:k], lens[:k], k, r.error_offset, r.nslices
+
     def cert_bitmap(self, data, mode: int = abi.LEX_MODE_EXACT):
         import torch
 

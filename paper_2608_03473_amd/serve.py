@@ -6,8 +6,14 @@ others (each document of a batch is scanned independently: lex_run_batch).
 
 The server keeps the lexers' tables resident (one lex_batch) and runs K slots.  A slot
 owns a stream (default priority), preallocated device buffers (input, kinds, lengths,
-document table, results, workspace) and pinned host staging; the slots split the HBM
-budget, and a request reserves 6 n + 64 bytes of it (input, worst-case output, result).
+document table, results, workspace) and pinned host staging.  Admission is against the HBM
+budget: every slot's device memory -- 6 bytes per input byte of its capacity (input and
+worst-case output, since a scan has at most one token per byte), 48 bytes per document
+record and result, and the batch workspace for that capacity -- counts against it, and
+the slot capacity is the largest (up to slot_cap) for which the K slots fit.  A request
+larger than a slot, or one arriving while the queue of admitted requests waiting for a
+slot already holds max_pending_bytes, is refused at once with a status (LEX_ELIMIT or
+LEX_ENOMEM) instead of being queued; it completes with no tokens.
 Whenever a slot is free, every request that has arrived and fits joins one batch: the
 payloads are gathered into the slot's pinned stage, copied to the device in one transfer,
 scanned by one lex_run_batch, and the outputs copied back into pinned memory, all on the
@@ -72,7 +78,8 @@ class Server:
     """K slots over one lex_batch; see the module notes."""
 
     def __init__(self, instances, budget_bytes: int = 16 << 30, slots: int = 4, max_docs: int = 8192,
-                 lane_bytes: int = 1024, device: int = 0, slot_cap: int = 16 << 20):
+                 lane_bytes: int = 1024, device: int = 0, slot_cap: int = 16 << 20,
+                 max_pending_bytes: int | None = None):
         import torch
 
         self.torch = torch
@@ -80,16 +87,23 @@ class Server:
         self.batch = Batch(instances)
         self.opts = abi.RunOpts(lane_bytes=lane_bytes)
         self.max_docs = max_docs
-        # a slot admits up to slot_bytes of input; its reservation, 6 bytes per input byte plus
-        # 64 per document, keeps all slots within the budget
+        # a slot admits up to slot_bytes of input; its device memory (input and worst-case
+        # output, document records and results, workspace) counts against the budget
         per_slot = budget_bytes // slots
-        self.slot_bytes = min(slot_cap, (per_slot - 64 * max_docs) // 6)
-        if self.slot_bytes <= 0:
+        n = min(slot_cap, per_slot // 6) & ~15
+        while n >= 4096 and self.slot_device_bytes(n) > per_slot:
+            n = (n * 7 // 8) & ~15
+        if n < 4096 or self.slot_device_bytes(n) > per_slot:
             raise ValueError("budget too small for the slots")
+        self.slot_bytes = n
+        self.reserved_bytes = slots * self.slot_device_bytes(n)
+        self.budget_bytes = budget_bytes
+        self.max_pending_bytes = max_pending_bytes if max_pending_bytes is not None else 8 * slots * n
+        self.pending_bytes = 0
+        self.refused: list[Request] = []
         self.max_busy = 0
         self.slots = []
         for _ in range(slots):
-            n = self.slot_bytes
             ws_n = self.batch.workspace_size(max_docs, n, self.opts)
             self.slots.append(_Slot(
                 stream=torch.cuda.Stream(device=self.dev),
@@ -110,15 +124,31 @@ class Server:
         self.pending: deque[Request] = deque()
         self.batch_sizes: list[int] = []
 
+    def slot_device_bytes(self, n: int) -> int:
+        """Device bytes of a slot of capacity n: input, kinds and lengths (6 n), document
+        records and results (48 per document), and the batch workspace."""
+        return 6 * n + 48 * self.max_docs + self.batch.workspace_size(self.max_docs, n, self.opts)
+
     # ------------------------------------------------------------- scheduling
-    def admit(self, req: Request, now: float):
-        if req.payload.size > self.slot_bytes:
-            raise ValueError("request larger than a slot")
+    def admit(self, req: Request, now: float) -> bool:
+        """Queues the request for the next free slot, or refuses it at once: LEX_ELIMIT when
+        it is larger than a slot, LEX_ENOMEM when the queue already holds max_pending_bytes.
+        A refused request completes (with its status, no tokens) at the next step."""
         req.admitted = now
+        size = req.payload.size
+        if size > self.slot_bytes or self.pending_bytes + size > self.max_pending_bytes:
+            req.status = abi.LEX_ELIMIT if size > self.slot_bytes else abi.LEX_ENOMEM
+            req.done = now
+            req.kinds = np.zeros(0, np.uint8)
+            req.lens = np.zeros(0, np.uint32)
+            self.refused.append(req)
+            return False
         self.pending.append(req)
+        self.pending_bytes += size
+        return True
 
     def busy(self) -> bool:
-        return bool(self.pending) or any(s.batch for s in self.slots)
+        return bool(self.pending) or bool(self.refused) or any(s.batch for s in self.slots)
 
     def _launch(self, slot: _Slot):
         torch = self.torch
@@ -127,6 +157,7 @@ class Server:
             r = self.pending.popleft()
             reqs.append(r)
             nbytes += r.payload.size
+        self.pending_bytes -= nbytes
         if not reqs:
             return
         docs = np.zeros(len(reqs), dtype=DOC_DTYPE)
@@ -191,7 +222,8 @@ class Server:
     def step(self, now_fn) -> list:
         """Completes finished slots and launches batches on free ones; returns the requests
         completed in this step."""
-        done = []
+        done = self.refused
+        self.refused = []
         for s in self.slots:
             if s.batch and s.event.query():
                 self._complete(s, now_fn(), done)
@@ -259,7 +291,8 @@ def open_loop(server: Server, pool, rate: float, seconds: float, seed: int, warm
     finally:
         if gc_was:
             gc.enable()
-    meas = [r for r in completed if r.arrival >= warmup]
+    refused = [r for r in completed if r.arrival >= warmup and r.status in (abi.LEX_ELIMIT, abi.LEX_ENOMEM)]
+    meas = [r for r in completed if r.arrival >= warmup and r.status not in (abi.LEX_ELIMIT, abi.LEX_ENOMEM)]
     lat = np.array([r.done - r.arrival for r in meas]) * 1e6
     wait = np.array([r.admitted - r.arrival for r in meas]) * 1e6
     nbytes = sum(r.payload.size for r in meas)
@@ -274,7 +307,10 @@ def open_loop(server: Server, pool, rate: float, seconds: float, seed: int, warm
         "batch_size_p50": float(np.percentile(server.batch_sizes, 50)) if server.batch_sizes else 0,
         "batch_size_max": int(max(server.batch_sizes)) if server.batch_sizes else 0,
         "errors": int(sum(r.status != 0 for r in meas)),
+        "refused": len(refused),
         "max_slots_busy": server.max_busy,
+        "slot_bytes": server.slot_bytes,
+        "reserved_device_bytes": server.reserved_bytes,
     }
     server.batch_sizes.clear()
     return (out, completed) if keep else out

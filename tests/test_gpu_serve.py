@@ -98,3 +98,39 @@ def test_large_batches_split_by_views():
         assert r.status == 0 and r.error_offset == con and r.ntokens == len(k), r.rid
         np.testing.assert_array_equal(r.kinds, k, err_msg=f"request {r.rid}")
         np.testing.assert_array_equal(r.lens, l, err_msg=f"request {r.rid}")
+
+
+def test_admission_against_the_budget():
+    """Every slot's device memory (input, worst-case outputs, document records, workspace)
+    fits the HBM budget; a request larger than a slot is refused with LEX_ELIMIT and one
+    arriving while the waiting queue is full with LEX_ENOMEM, each at once and with no
+    tokens, while every admitted request still equals the oracle's scan."""
+    from paper_2608_03473_amd import serve
+
+    budget = 64 << 20
+    server = serve.Server(serve.instances(), budget_bytes=budget, slots=2, max_docs=64, slot_cap=1 << 20,
+                          max_pending_bytes=256 << 10)
+    assert server.reserved_bytes <= budget and server.slot_bytes <= 1 << 20
+    pool = serve.make_pool(20, 14, median=16384, hi=128 << 10)
+    big = (0, np.frombuffer(b"x = 1;\n" * ((server.slot_bytes // 7) + 10), np.uint8).copy())
+    reqs = [serve.Request(i, inst, b, 0.0) for i, (inst, b) in enumerate(pool)]
+    reqs.append(serve.Request(len(reqs), big[0], big[1], 0.0))
+    admitted = [server.admit(r, 0.0) for r in reqs]
+    assert not admitted[-1] and reqs[-1].status == P.LEX_ELIMIT
+    assert not all(admitted[:-1])  # the queue bound refused some of the pool
+    done = []
+    while server.busy():
+        done += server.step(lambda: 0.0)
+    print(f"[case] serving admission: slot {server.slot_bytes} B, reserved {server.reserved_bytes} B, "
+          f"refused {sum(not a for a in admitted)}", flush=True)
+    assert len(done) == len(reqs)
+    orcs = [oracle.OracleSet(T.as_tuples(d)) for d, _ in SETS]
+    for r, ok in zip(reqs, admitted):
+        if not ok:
+            assert r.status in (P.LEX_ELIMIT, P.LEX_ENOMEM) and r.ntokens == 0 and r.kinds.size == 0
+            continue
+        defs, disc = SETS[r.inst]
+        k, l, con = orcs[r.inst].lex(bytes(r.payload), discard=disc)
+        assert r.status == 0 and r.error_offset == con and r.ntokens == len(k), r.rid
+        np.testing.assert_array_equal(r.kinds, k, err_msg=f"request {r.rid}")
+        np.testing.assert_array_equal(r.lens, l, err_msg=f"request {r.rid}")
