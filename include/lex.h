@@ -199,6 +199,25 @@ int lex_run(const lex_dfa *dfa, const uint8_t *d_bytes, uint64_t n, int mode, ui
             uint32_t *d_lens, uint64_t *d_offsets, uint64_t cap, lex_result *d_result, void *d_ws,
             size_t ws_bytes, const lex_run_opts *opts, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): lex_run with the workspace taken from
+ * scratch memory the library holds itself, LEX_STATIC_WS_BYTES on each device it runs on,
+ * reserved when the library's device code is loaded there and held until the process
+ * ends.  Arguments, outputs, asynchrony and results are those of lex_run (the same
+ * kernels run); the call allocates nothing (no hipMalloc, hipFree or allocating library
+ * routine).  Returns LEX_ELIMIT when the scan needs more workspace than
+ * LEX_STATIC_WS_BYTES (lex_workspace_size with the same arguments says how much; with
+ * default options inputs up to about 200 MiB fit), and
+ * LEX_EDEVICE when the lexer's tables are not yet on the current device (lex_compile
+ * uploads them when a device is present; otherwise one ordinary lex_run on that device
+ * does).  Every call on one device shares that device's scratch memory: calls whose
+ * scans overlap on one device (different streams, or host threads without ordering)
+ * race and give unspecified results; calls in order on one stream are safe. */
+#define LEX_STATIC_WS_BYTES (64u << 20)
+int lex_run_static(const lex_dfa *dfa, const uint8_t *d_bytes, uint64_t n, int mode, uint8_t *d_kinds,
+                   uint32_t *d_lens, uint64_t *d_offsets, uint64_t cap, lex_result *d_result,
+                   const lex_run_opts *opts, void *stream);
+
 /* ---- Batched documents (many independent scans in one launch sequence).
  *
  * A lex_batch holds up to 8 (lexer, mode) instances resident together on the current

@@ -35,6 +35,7 @@ class Info(C.Structure):
 
 
 LEX_NPHASES = 4
+LEX_STATIC_WS_BYTES = 64 << 20  # scratch of lex_run_static per device
 LEX_EMIT_DEFAULT, LEX_EMIT_LANE = 0, 1
 
 
@@ -76,6 +77,7 @@ def lib():
         "lex_workspace_size": (SZ, [P, U64, C.c_int, P]),
         "lex_plan": (C.c_int, [P, U64, C.c_int, P, P]),
         "lex_run": (C.c_int, [P, P, U64, C.c_int, P, P, P, U64, P, P, SZ, P, P]),
+        "lex_run_static": (C.c_int, [P, P, U64, C.c_int, P, P, P, U64, P, P, P]),
         "lex_cpu_chunked": (C.c_int, [P, P, U64, C.c_int, P, P, U64, U64, U32, C.POINTER(Result)]),
         "lex_cert_bitmap": (C.c_int, [P, P, U64, C.c_int, P, P]),
         "lex_batch_create": (C.c_int, [P, P, U32, P, C.c_char_p, SZ]),
@@ -99,7 +101,7 @@ def check(rc: int, msg: str = ""):
 
 def exported_symbols():
     return sorted(n for n in ("lex_compile", "lex_compile_framed", "lex_compile_table", "lex_free", "lex_cert", "lex_info",
-                              "lex_tables", "lex_workspace_size", "lex_plan", "lex_run", "lex_cpu_chunked",
+                              "lex_tables", "lex_workspace_size", "lex_plan", "lex_run", "lex_run_static", "lex_cpu_chunked",
                               "lex_cert_bitmap",
                               "lex_batch_create", "lex_batch_free", "lex_batch_workspace_size",
                               "lex_run_batch"))

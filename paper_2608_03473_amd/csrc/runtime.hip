@@ -77,6 +77,14 @@ void release(lex_dfa *d) {
   delete d;
 }
 
+// Device copy of d's tables on device dev if one was uploaded, else nullptr (no upload).
+DevCopy *find_copy(const lex_dfa *d, int dev) {
+  std::lock_guard<std::mutex> g(const_cast<lex_dfa *>(d)->mu);
+  for (DevCopy *c : d->copies)
+    if (c->device == dev) return c;
+  return nullptr;
+}
+
 // Device copy of d's tables on the current device, uploading them on first use.
 DevCopy *device_copy(lex_dfa *d) {
   int dev = -1;
@@ -400,6 +408,35 @@ int enqueue_scan(const lex_dfa *d, DevCopy *dc, const Resolved &r, const uint8_t
 // The host tables of a compiled lexer, for the host-side chunked baseline (cpu_chunked.cc).
 const lexc::Compiled &lex_compiled(const lex_dfa *d) { return d->c; }
 
+// Workspace of lex_run_static: one copy of this array on every device the library runs on
+// (the device globals of a code object are instantiated per device), held until the
+// process ends.  Host code never uses the name itself as an address: it is a host-side
+// stand-in, so each device's address is looked up once with that device current and kept.
+static __device__ __align__(256) uint8_t scratch[LEX_STATIC_WS_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[kMaxDevices] = {};  // scratch's address on each device, once looked up
+
+void *scratch_on(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_scratch[dev] = ptr;
+  }
+  return g_scratch[dev];
+}
+
+}  // namespace
+
 extern "C" {
 
 int lex_run(const lex_dfa *d, const uint8_t *d_bytes, uint64_t n, int mode, uint8_t *d_kinds, uint32_t *d_lens,
@@ -416,6 +453,26 @@ int lex_run(const lex_dfa *d, const uint8_t *d_bytes, uint64_t n, int mode, uint
   return enqueue_scan(d, dc, r, d_bytes, n, d_kinds, d_lens, d_offsets, cap, d_result, d_ws, ws_bytes, opts, stream);
 }
 
+int lex_run_static(const lex_dfa *d, const uint8_t *d_bytes, uint64_t n, int mode, uint8_t *d_kinds,
+                   uint32_t *d_lens, uint64_t *d_offsets, uint64_t cap, lex_result *d_result,
+                   const lex_run_opts *opts, void *stream) {
+  int rc = check_scan_args(d, d_bytes, n, d_kinds, d_lens, cap, d_result);
+  if (rc != LEX_OK) return rc;
+  Resolved r;
+  rc = resolve(d, n, mode, opts, r);
+  if (rc != LEX_OK) return rc;
+  const size_t need =
+      lexk::workspace_bytes((uint32_t)n, r.lane_bytes, r.block, r.path == 1 && !r.hybrid, r.windowed, r.hybrid);
+  if (need > (size_t)LEX_STATIC_WS_BYTES) return LEX_ELIMIT;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return LEX_EDEVICE;
+  DevCopy *dc = find_copy(d, dev);  // never uploads: that would allocate
+  if (!dc) return LEX_EDEVICE;
+  void *ws = scratch_on(dev);
+  if (!ws) return LEX_EDEVICE;
+  return enqueue_scan(d, dc, r, d_bytes, n, d_kinds, d_lens, d_offsets, cap, d_result, ws, (size_t)LEX_STATIC_WS_BYTES,
+                      opts, stream);
+}
 
 int lex_batch_create(const lex_dfa *const *dfas, const int32_t *modes, uint32_t ninst, lex_batch **out, char *err,
                      size_t errlen) {

@@ -165,6 +165,20 @@ class Lexer:
                                C.byref(opts) if opts else None, C.c_void_p(s.cuda_stream))
         abi.check(rc, "lex_run")
 
+    def run_static_into(self, data, n: int, mode: int, kinds, lens, offsets, cap: int, result,
+                        opts: abi.RunOpts | None = None, stream=None):
+        """As run_into, with the library's own scratch as workspace (lex_run_static): for
+        callers that cannot allocate.  Scans that overlap on one device race."""
+        import torch
+
+        s = stream if stream is not None else torch.cuda.current_stream()
+        rc = abi.lib().lex_run_static(self._h, data.data_ptr() if n else None, n, mode,
+                                      kinds.data_ptr() if cap else None, lens.data_ptr() if cap else None,
+                                      offsets.data_ptr() if offsets is not None else None, cap,
+                                      result.data_ptr(), C.byref(opts) if opts else None,
+                                      C.c_void_p(s.cuda_stream))
+        abi.check(rc, "lex_run_static")
+
     def run(self, data, mode: int = abi.LEX_MODE_EXACT, offsets: bool = False, cap: int | None = None,
             opts: abi.RunOpts | None = None) -> RunResult:
         """Scans a 1-D uint8 CUDA tensor; synchronises once to read the result."""
