@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=4.0, help="per arrival rate (plus 1 s warm-up)")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the 1 MiB, 256 MiB JSON and stray-byte configuration legs")
+    ap.add_argument("--only", choices=["framed"], default=None,
+                    help="run that leg alone (no headline scan): for kernel traces and counters")
     ap.add_argument("--cpu-threads", type=int, default=0,
                     help="threads of the chunked CPU baseline's all-cores figure (0: the cores this process may use)")
     ap.add_argument("--copy-ref", action="store_true",
@@ -76,6 +78,9 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     n = args.n
+    if args.only == "framed":
+        print(json.dumps({"framed": framed_leg(args)}), flush=True)
+        return
     t0 = time.time()
     host = workloads.clike(n, args.seed)
     log(args, f"corpus: {n} bytes in {time.time() - t0:.1f}s")
@@ -525,6 +530,11 @@ def framed_leg(args):
     for key, lx, frame in (("framed", P.Lexer.compile_framed(defs), 8), ("unframed", P.Lexer.compile(defs), 0)):
         host = workloads.clike(n, args.seed, bcomment=True, frame=frame)
         data = torch.from_numpy(host).to(dev)
+        if args.copy_ref and frame:  # a plain copy of n bytes, to scale HBM counters
+            ref = torch.empty_like(data)
+            torch.bitwise_or(data, 0, out=ref)
+            torch.cuda.synchronize()
+            del ref
         ws = torch.empty(lx.workspace_size(n, mode), dtype=torch.uint8, device=dev)
         for _ in range(args.warmup):
             lx.run_into(data, n, mode, kinds, lens, None, n, res, ws, None, stream)
