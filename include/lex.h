@@ -143,8 +143,8 @@ int lex_tables(const lex_dfa *dfa, int mode, uint32_t *table, size_t table_entri
  * emit, all in one launch; 0 = default: 3 where it applies, else 2.  block_threads:
  * threads per walk workgroup, 256, 512 or 1024 (0 = the largest whose LDS fits; one pass
  * uses 256 and a default path given another value takes path 2).  emit: 0 = default,
- * 1 = lane emit only.  By default a scan that counts every token end in its mode (exact
- * mode, or no discarded kind) and has at most 256 rows uses the windowed emit: the count
+ * 1 = lane emit only.  By default a scan of an automaton with at most 256 rows uses the
+ * windowed emit: the count
  * walk records checkpoints every 64 bytes and the emit walk runs one thread per 64-byte
  * sub-slice; a scan with a halted slice or a slice of 2^24 bytes or more falls back to the
  * lane emit (one thread per slice) on the device, and so does a scan of a non-monotone

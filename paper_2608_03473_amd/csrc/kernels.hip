@@ -23,9 +23,10 @@
 //                    Tokens are staged in a 64-byte per-lane LDS ring and leave in whole,
 //                    aligned 32-byte sectors (8 lengths or 32 kinds at a time), so the
 //                    emit walk issues few, full-width memory requests.
-//       k_emit_win   the windowed emit (monotone automata whose token ends are all
-//                    counted): one thread per 64-byte window, restarted from the count
-//                    walk's checkpoint, tokens staged per wave and written out coalesced.
+//       k_emit_win   the windowed emit: one thread per 64-byte window, restarted from
+//                    the count walk's checkpoint, tokens staged per wave (their ends, or
+//                    their lengths in a mode with discarded kinds) and written out
+//                    coalesced.
 //   k_onepass        (b)-(e) for windowed scans in one launch: 256-lane groups taken in
 //                    order plan, count, find their first output slot by a decoupled
 //                    look-back over the earlier groups' totals, and emit their windows.
@@ -630,19 +631,21 @@ __device__ __forceinline__ void block16(LaneState &L, Ring &r, const Tables &tb,
     return;
   }
   if (!EMIT && MONO) {
-    // count walk of a monotone automaton: the COUNT bits of the 16 steps are shifted
-    // into m (bit 0 of each entry lands in bit 31) and popcounted once.
+    // count walk of a monotone automaton: the COUNT and EMIT bits of the 16 steps are
+    // shifted into m (step k's pair lands in bits 2k, 2k + 1) and the COUNT bits popcounted
+    // once.
     uint32_t m = 0, e = L.st;
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
       e = entry_from(tb, e, byte_of(v, k));
-      m = __builtin_amdgcn_alignbit(e, m, 1);
+      m = __builtin_amdgcn_alignbit(e, m, 2);
     }
     L.st = e & kRowMask;
-    L.cnt += __builtin_popcount(m);
-    // start of the token in progress: the last step whose token ended (bit 16 + k
-    // holds step k); only read by checkpoints, whose tables count every token end
-    L.tok = m ? blk + 15 - __clz(m) : L.tok;
+    L.cnt += __builtin_popcount(m & 0x55555555u);
+    // start of the token in progress: the last step at which a token ended, kept or
+    // discarded (only read by checkpoints)
+    const uint32_t me = m & 0xAAAAAAAAu;
+    L.tok = me ? blk + ((31 - __clz(me)) >> 1) : L.tok;
     return;
   }
   if (EMIT && FAST) {
@@ -847,11 +850,13 @@ __device__ __forceinline__ bool walk_lines(LaneState &L, Ring &r, const Tables &
           const int q = 16 * i + k;
           const uint32_t y = entry_from(tb, st, byte_of(v[i], k));
           st = q < lo ? tb.start : q < hi ? y : st;
-          m = __builtin_amdgcn_alignbit(y, m, 1);
+          m = __builtin_amdgcn_alignbit(y, m, 2);
         }
-        m &= range_word(lo - 16 * i + 16, hi - 16 * i + 16, 0) & 0xFFFF0000u;  // bit 16 + k: step 16 i + k
-        L.cnt += __builtin_popcount(m);
-        L.tok = m ? blk + 16 * i + 15 - __clz(m) : L.tok;
+        // bits 2k, 2k + 1: COUNT and EMIT of step 16 i + k, kept for the steps in [lo, hi)
+        m &= range_word(2 * (lo - 16 * i), 2 * (hi - 16 * i), 0);
+        L.cnt += __builtin_popcount(m & 0x55555555u);
+        const uint32_t me = m & 0xAAAAAAAAu;
+        L.tok = me ? blk + 16 * i + ((31 - __clz(me)) >> 1) : L.tok;
       }
       L.st = st & kRowMask;
     }
@@ -1343,7 +1348,9 @@ struct WinOut {
 };
 
 // st carries the previous entry unmasked (or a row state); mask it before reading a row.
-template <bool STAGED>
+// DISC: some token ends are not counted (discarded kinds), so a staged word holds the kept
+// token's length, p - tok, instead of its end (a length is then no difference of ends).
+template <bool STAGED, bool DISC>
 __device__ __forceinline__ void win_step(const Tables &tb, const WalkArgs &a, uint32_t &st, WinOut &w, uint32_t b,
                                          uint32_t p) {
   const uint32_t e = entry_from(tb, st, b);
@@ -1354,8 +1361,10 @@ __device__ __forceinline__ void win_step(const Tables &tb, const WalkArgs &a, ui
     // ends saves LDS traffic but costs more in exec-mask handling than it saves.)
     const uint32_t c = e & kCountBit;
     __builtin_assume(w.D < 4 * kStageWords);  // the slots lie above the spill words
-    *(lds_u32 *)(size_t)(__umul24(c, w.D) + w.G) = __builtin_amdgcn_perm(e, p - w.base, 0x02010007u);
+    *(lds_u32 *)(size_t)(__umul24(c, w.D) + w.G) =
+        __builtin_amdgcn_perm(e, p - (DISC ? w.tok : w.base), 0x02010007u);
     w.D += c << 2;
+    if (DISC) w.tok = (e & kEmitBit) ? p : w.tok;
   } else {
     if ((e & kCountBit) && w.o < w.lim) {
       a.kinds[w.o] = (uint8_t)(e >> 24);
@@ -1386,7 +1395,7 @@ __device__ __forceinline__ Win64 win_load(const uint8_t *in, int64_t wp, uint32_
 }
 
 // Walks the window [wp, wp + 64) ∩ [0, n).  EDGE: some positions may lie outside.
-template <bool STAGED, bool EDGE>
+template <bool STAGED, bool EDGE, bool DISC>
 __device__ __forceinline__ void win_walk(const Tables &tb, const WalkArgs &a, const Win64 &d, int64_t wp,
                                          uint32_t n, uint32_t &st, WinOut &w) {
   const uint32_t p0 = (uint32_t)wp;  // positions p0 + k modulo 2^32; only those in [0, n) are walked
@@ -1395,7 +1404,8 @@ __device__ __forceinline__ void win_walk(const Tables &tb, const WalkArgs &a, co
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
       const int64_t p = wp + 16 * q + k;
-      if (!EDGE || (p >= 0 && p < (int64_t)n)) win_step<STAGED>(tb, a, st, w, byte_of(d.v[q], k), p0 + 16 * q + k);
+      if (!EDGE || (p >= 0 && p < (int64_t)n))
+        win_step<STAGED, DISC>(tb, a, st, w, byte_of(d.v[q], k), p0 + 16 * q + k);
     }
   }
 }
@@ -1407,7 +1417,9 @@ __device__ __forceinline__ void win_walk(const Tables &tb, const WalkArgs &a, co
 // slot when known); next_fresh: a lane starts at the next window's first byte; P: start of
 // the token in progress at the tile's start; span_end: end of the tile's bytes; lim: no
 // output at or above it.  Staged when the range fits the stage (see the kernel notes),
-// else each token goes straight to global memory.
+// else each token goes straight to global memory.  DISC (a mode with discarded kinds):
+// staged words hold lengths, and a scan that asks for offsets goes straight to memory.
+template <bool DISC>
 __device__ __forceinline__ void win_tile(const Tables &tb, const WalkArgs &a, uint32_t *stage, uint32_t lane,
                                          const WinMeta &cur, uint32_t i, bool valid, bool edge, const Win64 &dat,
                                          int64_t wp, uint32_t nwin, uint32_t o_first, uint32_t o_end, bool exact,
@@ -1418,9 +1430,10 @@ __device__ __forceinline__ void win_tile(const Tables &tb, const WalkArgs &a, ui
   // 0, the start of the tile's first token (so every length is a difference of ends)
   const uint32_t pad = (o_first & 3) + 4;
   const bool staged = o_first <= o_end && o_end <= lim && o_end - o_first + pad + 3 <= kStageWords - 64 &&
-                      span_end - P < (1u << 24);
+                      span_end - P < (1u << 24) && !(DISC && a.offs);
   uint32_t st = cur.st;
   WinOut w;
+  w.tok = cur.tok;
   uint32_t d0 = 0;
   if (staged) {
     // spill words: the stage's first 64; slots follow, so 0 < D < 4 * kStageWords
@@ -1429,16 +1442,15 @@ __device__ __forceinline__ void win_tile(const Tables &tb, const WalkArgs &a, ui
     w.base = P;
     if (lane == 0) stage[64 + pad - 1] = 0;
     if (valid) {
-      if (edge) win_walk<true, true>(tb, a, dat, wp, a.n, st, w);
-      else win_walk<true, false>(tb, a, dat, wp, a.n, st, w);
+      if (edge) win_walk<true, true, DISC>(tb, a, dat, wp, a.n, st, w);
+      else win_walk<true, false, DISC>(tb, a, dat, wp, a.n, st, w);
     }
   } else {
-    w.tok = cur.tok;
     w.o = cur.out;
     w.lim = valid ? min(out_end, lim) : cur.out;
     if (valid) {
-      if (edge) win_walk<false, true>(tb, a, dat, wp, a.n, st, w);
-      else win_walk<false, false>(tb, a, dat, wp, a.n, st, w);
+      if (edge) win_walk<false, true, DISC>(tb, a, dat, wp, a.n, st, w);
+      else win_walk<false, false, DISC>(tb, a, dat, wp, a.n, st, w);
     }
   }
   // The input's end, or a lane starting at the next window's first byte: the token in
@@ -1450,7 +1462,7 @@ __device__ __forceinline__ void win_tile(const Tables &tb, const WalkArgs &a, ui
     const uint32_t row = st >> kRowShift;
     if ((tb.info[row] & kInfoAcc) && (tb.info[row] & kInfoCount)) {
       if (staged) {
-        *(lds_u32 *)(size_t)(w.G + w.D) = (uint32_t)tb.kind[row] | ((end - P) << 8);
+        *(lds_u32 *)(size_t)(w.G + w.D) = (uint32_t)tb.kind[row] | ((end - (DISC ? w.tok : P)) << 8);
         w.D += 4;
       } else if (w.o < w.lim) {
         a.kinds[w.o] = tb.kind[row];
@@ -1465,13 +1477,14 @@ __device__ __forceinline__ void win_tile(const Tables &tb, const WalkArgs &a, ui
                                : wave_max(valid ? cur.out - o_first + (w.D - d0) / 4 : 0);
   wave_sync();
   // write the range out, four slots per lane and step: lengths are differences of
-  // consecutive ends (slot pad - 1 holds 0), kinds the low bytes
+  // consecutive ends (slot pad - 1 holds 0) or, DISC, the words themselves; kinds the low
+  // bytes
   const uint32_t o0 = o_first - pad;
   const uint32_t *slots = stage + 64;
   for (uint32_t q = 4 + lane * 4; q < pad + total; q += 256) {
     const uint4 v = *reinterpret_cast<const uint4 *>(slots + q);
-    const uint32_t e0 = slots[q - 1] >> 8, e1 = v.x >> 8, e2 = v.y >> 8, e3 = v.z >> 8, e4 = v.w >> 8;
-    const uint4 len = make_uint4(e1 - e0, e2 - e1, e3 - e2, e4 - e3);
+    const uint32_t e0 = DISC ? 0 : slots[q - 1] >> 8, e1 = v.x >> 8, e2 = v.y >> 8, e3 = v.z >> 8, e4 = v.w >> 8;
+    const uint4 len = DISC ? make_uint4(e1, e2, e3, e4) : make_uint4(e1 - e0, e2 - e1, e3 - e2, e4 - e3);
     const uint32_t kd = __builtin_amdgcn_perm(__builtin_amdgcn_perm(v.w, v.z, 0x0C0C0400u),
                                               __builtin_amdgcn_perm(v.y, v.x, 0x0C0C0400u), 0x05040100u);
     const uint32_t o = o0 + q;
@@ -1501,7 +1514,7 @@ __device__ __forceinline__ void win_tile(const Tables &tb, const WalkArgs &a, ui
 
 // A tile is 64 windows; each wave walks a contiguous run of tiles.  Software pipeline:
 // the next tile's bytes and the state of the tile after it load while a tile walks.
-template <bool FUSED>
+template <bool FUSED, bool DISC>
 __global__ void __launch_bounds__(256) k_emit_win(WalkArgs a) {
   if (a.meta[0] != kNone || a.meta[1] != 0 || a.res->status != 0 || a.n == 0) return;
   const Lds l = carve_lds(a.nrows);
@@ -1541,8 +1554,8 @@ __global__ void __launch_bounds__(256) k_emit_win(WalkArgs a) {
     const uint32_t f_next = __shfl(nxt.fresh, 0);
     const uint32_t P = __shfl(cur.tok, 0);  // start of the token in progress at the tile's start
     const uint32_t span_end = (uint32_t)min<int64_t>((int64_t)(tile + 1) * 64 * kWin - mis0, a.n);
-    win_tile(tb, a, stage, lane, cur, i, i < nwin, is_edge(tile), dat, wpos(tile), nwin, o_first, o_next, true,
-             lane < 63 ? down : o_next, lane < 63 ? fdown : f_next, P, span_end, ntok);
+    win_tile<DISC>(tb, a, stage, lane, cur, i, i < nwin, is_edge(tile), dat, wpos(tile), nwin, o_first, o_next,
+                   true, lane < 63 ? down : o_next, lane < 63 ? fdown : f_next, P, span_end, ntok);
     cur = nxt;
     nxt = n2;
     dat = ndat;
@@ -1620,7 +1633,8 @@ __device__ __forceinline__ WinMeta group_meta(const WalkArgs &a, const GroupLds 
   return m;
 }
 
-__global__ void __launch_bounds__(256) k_onepass(WalkArgs a) {
+template <bool DISC>
+__global__ void __launch_bounds__(256, 4) k_onepass(WalkArgs a) {  // four waves per SIMD: at most 128 VGPRs
   const Lds l = carve_lds(a.nrows);
   stage_tables(a, l, true);
   const Tables tb{lds_bytes_of(l.T), l.info, l.kind, a.sink, a.fail, 0};
@@ -1786,8 +1800,8 @@ __global__ void __launch_bounds__(256) k_onepass(WalkArgs a) {
           const uint32_t lastv = min(63u, i_hi - 1 - (i_lo + t * 64));
           const uint32_t o_end = exact ? o_next : __shfl(cur.out, lastv) + 65;
           const uint32_t span_end = (uint32_t)min<uint64_t>((uint64_t)(i_lo + t * 64 + 64) * kWin - mis0, a.n);
-          win_tile(tb, a, stage, lane, cur, i, i < i_hi, is_edge(t), dat, wpos(t), nwin, o_first, o_end, exact,
-                   lane < 63 ? down : o_next, lane < 63 ? fdown : f_next, P, span_end, cap);
+          win_tile<DISC>(tb, a, stage, lane, cur, i, i < i_hi, is_edge(t), dat, wpos(t), nwin, o_first, o_end,
+                         exact, lane < 63 ? down : o_next, lane < 63 ? fdown : f_next, P, span_end, cap);
           cur = nxt;
           nxt = n2;
           dat = ndat;
@@ -2823,7 +2837,10 @@ static hipError_t count_scan_emit(const DevTable &t, const WalkArgs &a0, const P
   mark(ev, 3, s);
   if (win) {
     const uint32_t ntiles = (windows_max(p.n) + 63) / 64;
-    k_emit_win<FUSED><<<win_grid(t.nrows, ntiles), kWinWaves * 64, win_lds_bytes(t.nrows), s>>>(a);
+    if (t.all_counted)
+      k_emit_win<FUSED, false><<<win_grid(t.nrows, ntiles), kWinWaves * 64, win_lds_bytes(t.nrows), s>>>(a);
+    else
+      k_emit_win<FUSED, true><<<win_grid(t.nrows, ntiles), kWinWaves * 64, win_lds_bytes(t.nrows), s>>>(a);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     a.fallback_only = 1;  // halted scans and long slices
@@ -3046,7 +3063,8 @@ hipError_t run_onepass(const DevTable &t, const CertMap &cm, const uint8_t *cert
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   mark(ev, 1, s);
-  k_onepass<<<grid, kChunkLanes, lds, s>>>(a);
+  if (t.all_counted) k_onepass<false><<<grid, kChunkLanes, lds, s>>>(a);
+  else k_onepass<true><<<grid, kChunkLanes, lds, s>>>(a);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   mark(ev, 2, s);

@@ -192,10 +192,10 @@ int resolve(const lex_dfa *d, uint64_t n, int mode, const lex_run_opts *o, Resol
   if (asked == 3 && bt && bt != (int32_t)lexk::kChunkLanes) return LEX_EINVAL;
   const int emit = o ? o->emit : LEX_EMIT_DEFAULT;
   if (emit != LEX_EMIT_DEFAULT && emit != LEX_EMIT_LANE) return LEX_EINVAL;
-  // The windowed emit needs every token end counted; a non-monotone automaton also needs a
-  // scan without fallbacks, which the count walk reports (the lane emit then runs instead).
-  r.windowed = emit == LEX_EMIT_DEFAULT && d->all_counted[r.table] && d->c.nrows <= 256 &&
-               lexk::window_lds_bytes(d->c.nrows) <= 160 * 1024;
+  // The windowed emit: a non-monotone automaton needs a scan without fallbacks, which the
+  // count walk reports (the lane emit then runs instead).  In a mode with discarded kinds
+  // its staged words carry lengths, not ends.
+  r.windowed = emit == LEX_EMIT_DEFAULT && d->c.nrows <= 256 && lexk::window_lds_bytes(d->c.nrows) <= 160 * 1024;
   // By default (and as path 3) a monotone windowed scan runs in one pass when its workgroup
   // fits; every other scan takes the fused path unless the pipeline is asked for.
   r.onepass = (asked == 0 || asked == 3) && r.windowed && d->c.monotone && (!bt || bt == (int32_t)lexk::kChunkLanes) &&

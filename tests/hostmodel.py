@@ -18,6 +18,8 @@ class Model:
         # row states are kept as row index * 256, the index of the row's first entry
         self.sink = (1 + inf["nstates"]) * 256
         self.mono = bool(inf["monotone"])
+        # some token end of this mode is not counted (a discarded kind)
+        self.disc = bool((((self.T & EMIT) != 0) & ((self.T & COUNT) == 0)).any())
         self.fail = self.sink if self.mono else (2 + inf["nstates"]) * 256
 
     def walk(self, w: bytes, s: int, e: int, memo: int = 4, work=None):
@@ -152,16 +154,19 @@ def plan_fused(w: bytes, cert, lane: int):
 
 
 def windowed(model, w: bytes, starts, ends, lane: int, base: int, block: int = 4,
-             stage_words: int = 1280, W: int = 64):
+             stage_words: int = 1280, W: int = 64, offsets: bool = True):
     """The checkpointed count walk and the windowed emit of the library, restated.
 
     starts/ends: the lanes' slices (lane j nominally covers [j l, (j+1) l)).  base: the
     input's address modulo W.  block: lanes per count workgroup.  Returns (kinds, lens, offs),
     or None when a slice halts (the library then uses the lane emit).  Mirrors the kernels'
     bookkeeping: window checkpoints, owner lookup through the last-non-empty-lane prefixes,
-    64-window tiles, the staged words (end - P) << 8 | kind after 4 to 7 padding slots, and the
-    direct fallback for ranges longer than the stage.
+    64-window tiles, the staged words (end - P) << 8 | kind after 4 to 7 padding slots (in a
+    mode with discarded kinds, length << 8 | kind, and no staging when offsets are asked
+    for), and the direct fallback for ranges longer than the stage.  Without offsets the
+    third list is None.
     """
+    disc = model.disc
     T, info, kind = model.T, model.info, model.kind
     n, nl, mis0 = len(w), len(starts), base % W
     kslots = lane // W + 4
@@ -234,7 +239,8 @@ def windowed(model, w: bytes, starts, ends, lane: int, base: int, block: int = 4
         P = ms[0][1]
         total, pad = o_end - o_first, (o_first & 3) + 4
         span_end = min((tile + 1) * 64 * W - mis0, n)
-        staged = o_first <= o_end <= ntok and total + pad + 3 <= stage_words - 64 and span_end - P < (1 << 24)
+        staged = (o_first <= o_end <= ntok and total + pad + 3 <= stage_words - 64 and span_end - P < (1 << 24)
+                  and not (disc and offsets))
         stage = {pad - 1: 0}  # the end before the tile's first token: 0 relative to P
         for L, i in enumerate(ids):
             if i >= nwin:
@@ -246,14 +252,15 @@ def windowed(model, w: bytes, starts, ends, lane: int, base: int, block: int = 4
                 y = ent(st, w[p])
                 if staged:
                     if y & COUNT:
-                        stage[slot] = (((p - P) & 0xFFFFFF) << 8) | ((y >> 24) & 0xFF)
+                        v = p - tok if disc else p - P
+                        stage[slot] = ((v & 0xFFFFFF) << 8) | ((y >> 24) & 0xFF)
                         slot += 1
                 else:
                     if (y & COUNT) and o < lim:
                         kinds[o], lens[o], offs[o] = (y >> 24) & 0xFF, p - tok, tok
                         o += 1
-                    if y & EMIT:
-                        tok = p
+                if y & EMIT:
+                    tok = p
                 st = (y & ROWMASK) >> 2
             # the input's end, or a lane starting at the next window: the token ends here
             if (i + 1 == nwin or nxt[L][3]) and st != 0:
@@ -261,7 +268,7 @@ def windowed(model, w: bytes, starts, ends, lane: int, base: int, block: int = 4
                 r = st >> 8
                 if (info[r] & INFO_ACC) and (info[r] & INFO_COUNT):
                     if staged:
-                        stage[slot] = int(kind[r]) | ((end - P) << 8)
+                        stage[slot] = int(kind[r]) | ((end - (tok if disc else P)) << 8)
                     elif o < lim:
                         kinds[o], lens[o], offs[o] = int(kind[r]), end - tok, tok
         if not staged:
@@ -272,8 +279,11 @@ def windowed(model, w: bytes, starts, ends, lane: int, base: int, block: int = 4
             for k in range(4):
                 g = q + k
                 if pad <= g < pad + total:
-                    kinds[o0 + g], lens[o0 + g], offs[o0 + g] = stage[g] & 0xFF, ev[k + 1] - ev[k], P + ev[k]
-    return kinds, lens, offs
+                    if disc:  # the word holds the length; no offsets in this form
+                        kinds[o0 + g], lens[o0 + g], offs[o0 + g] = stage[g] & 0xFF, ev[k + 1], None
+                    else:
+                        kinds[o0 + g], lens[o0 + g], offs[o0 + g] = stage[g] & 0xFF, ev[k + 1] - ev[k], P + ev[k]
+    return kinds, lens, (offs if offsets else None)
 
 
 def spec_walk(model, w: bytes, b: int, end: int):

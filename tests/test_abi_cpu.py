@@ -96,8 +96,11 @@ def test_plan_query():
     assert cl.plan(512 << 20, opts=P.RunOpts(path=1))["path"] == 1
     assert cl.plan(512 << 20, opts=P.RunOpts(emit=P.LEX_EMIT_LANE)) ["path"] == 2
     assert cl.plan(512 << 20, opts=P.RunOpts(block_threads=1024))["path"] == 2  # default path, other block
-    j = js.plan(256 << 20, P.LEX_MODE_DISCARD)  # not monotone: no windowed emit, no one pass
-    assert j["path"] == 2 and j["windowed"] == 0
+    j = js.plan(256 << 20, P.LEX_MODE_DISCARD)  # not monotone: windowed emit, no one pass
+    assert j["path"] == 2 and j["windowed"] == 1
+    cd = P.Lexer.compile(T.as_tuples(T.CLIKE_D))  # discarded kinds, monotone: one pass
+    assert cd.plan(512 << 20, P.LEX_MODE_DISCARD)["path"] == 3
+    assert cd.plan(512 << 20, P.LEX_MODE_DISCARD)["windowed"] == 1
     assert js.plan(256 << 20, P.LEX_MODE_DISCARD, P.RunOpts(path=3))["path"] == 2
     with pytest.raises(P.LexError):
         cl.plan(1 << 20, opts=P.RunOpts(path=3, block_threads=1024))  # one pass uses 256

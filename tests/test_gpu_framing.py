@@ -61,9 +61,9 @@ def test_framed_document_splits_at_the_separator(sets, mode, path, lane):
     lx, oc = sets["lx"], sets["oc"]
     plan = lx.plan(DOC.size, mode, P.RunOpts(lane_bytes=lane, path=path))
     assert plan["hybrid"] == 0
-    # exact mode counts every token end: the windowed emit, on this non-monotone automaton
-    # (no slice of this document falls back); modulo I the lane emit
-    assert plan["windowed"] == (mode == P.LEX_MODE_EXACT) and plan["path"] in (1, 2)
+    # the windowed emit in both modes, on this non-monotone automaton (no slice of this
+    # document falls back; modulo I its staged words carry lengths)
+    assert plan["windowed"] == 1 and plan["path"] in (1, 2)
     r = check(lx, oc, DOC, mode, P.RunOpts(lane_bytes=lane, path=path))
     assert r.nslices > 1
     assert int((r.kinds.cpu().numpy() == len(DEFS)).sum()) == int((DOC == RS).sum())

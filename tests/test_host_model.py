@@ -76,7 +76,9 @@ def test_windowed_emit_model():
     cases = [("clike_l", bytes(workloads.clike(20000, 3)), 0),
              ("clike_l", bytes(workloads.clike(3000, 4)) + long_tok + bytes(workloads.clike(3000, 5)), 0),
              ("log", bytes(workloads.loglines(12000, 37)), 0),
-             ("clike_d", bytes(workloads.clike(9000, 6)), 0)]
+             ("clike_d", bytes(workloads.clike(9000, 6)), 0),
+             ("clike_d", bytes(workloads.clike(9000, 6)), 1),
+             ("clike_d", bytes(workloads.clike(3000, 4)) + long_tok.replace(b"/*", b"//") + bytes(workloads.clike(3000, 5)), 1)]
     for name, w, mode in cases:
         defs = T.as_tuples(T.NAMED[name])
         lx, oc = P.Lexer.compile(defs), oracle.OracleSet(defs)
@@ -92,6 +94,9 @@ def test_windowed_emit_model():
                     for stage in (1280, 150):
                         got = hostmodel.windowed(m, w, starts, ends, lane, base, 4, stage)
                         assert got == want, (name, lane, base, stage)
+                        # without offsets: a discarding mode stages lengths
+                        got = hostmodel.windowed(m, w, starts, ends, lane, base, 4, stage, offsets=False)
+                        assert got == want[:2] + (None,), (name, mode, lane, base, stage)
         # a slice that halts: the windowed emit stands down
         bad = w[:3000] + b"\x01" + w[3000:]
         if oc.lex(bad, discard=bool(mode))[2] < len(bad):
@@ -208,15 +213,20 @@ def test_windowed_emit_model_nonmonotone():
               bytes(workloads.json(30000, 8)))]
     for lx, oc, w in cases:
         assert not lx.info()["monotone"]
-        m = hostmodel.Model(lx, P.LEX_MODE_EXACT)
-        k, l, offs, con = oc.lex(w, offsets=True)
-        want = (k.tolist(), l.tolist(), offs.tolist())
-        cert = lx.cert(P.LEX_MODE_EXACT)
-        for lane in (64, 1024):
-            cuts = hostmodel.plan_cuts(w, cert, lane)
-            for starts, ends in [(cuts[:-1], cuts[1:]), hostmodel.plan_fused(w, cert, lane)]:
-                for base in (0, 5):
-                    assert hostmodel.windowed(m, w, starts, ends, lane, base, 4, 1280) == want, lane
+        for mode in (P.LEX_MODE_EXACT, P.LEX_MODE_DISCARD):
+            m = hostmodel.Model(lx, mode)
+            k, l, offs, con = oc.lex(w, discard=bool(mode), offsets=True)
+            want = (k.tolist(), l.tolist(), offs.tolist())
+            cert = lx.cert(mode)
+            if not cert:
+                continue
+            for lane in (64, 1024):
+                cuts = hostmodel.plan_cuts(w, cert, lane)
+                for starts, ends in [(cuts[:-1], cuts[1:]), hostmodel.plan_fused(w, cert, lane)]:
+                    for base in (0, 5):
+                        assert hostmodel.windowed(m, w, starts, ends, lane, base, 4, 1280) == want, lane
+                        got = hostmodel.windowed(m, w, starts, ends, lane, base, 4, 1280, offsets=False)
+                        assert got == want[:2] + (None,), (mode, lane)
     # a fallback inside a slice (an unterminated comment cut by a separator): stood down
     lx, oc, w = cases[0]
     bad = w[:5000] + b"/* x" + bytes([0x1E]) + w[5000:]
@@ -245,26 +255,29 @@ def test_windowed_emit_model_random_sets():
     oracle's, else it stands down.  Strings of whole tokens give non-monotone sets scans
     without fallbacks; random strings give both outcomes."""
     rng = random.Random(6)
-    ran = nonmono = 0
+    ran = nonmono = disc = 0
     for seed in range(200):
         defs = rand_set(seed, "abc") + [(";", 0, False)]
         lx, oc = P.Lexer.compile(defs), oracle.OracleSet(defs)
-        cert = lx.cert(P.LEX_MODE_EXACT)
-        if not cert:
-            continue
-        m = hostmodel.Model(lx, P.LEX_MODE_EXACT)
-        for w in (_token_string(oc, rng), bytes(rng.choice(b"abc;") for _ in range(600))):
-            if w is None:
+        for mode in (P.LEX_MODE_EXACT, P.LEX_MODE_DISCARD):
+            cert = lx.cert(mode)
+            if not cert:
                 continue
-            k, l, offs, con = oc.lex(w, offsets=True)
-            if con < len(w):
-                continue
-            want = (k.tolist(), l.tolist(), offs.tolist())
-            for lane in (16, 64):
-                cuts = hostmodel.plan_cuts(w, cert, lane)
-                got = hostmodel.windowed(m, w, cuts[:-1], cuts[1:], lane, 7)
-                if got is not None:
-                    ran += 1
-                    nonmono += not lx.info()["monotone"]
-                    assert got == want, (defs, lane)
-    assert ran > 100 and nonmono > 20, (ran, nonmono)
+            m = hostmodel.Model(lx, mode)
+            for w in (_token_string(oc, rng), bytes(rng.choice(b"abc;") for _ in range(600))):
+                if w is None:
+                    continue
+                k, l, offs, con = oc.lex(w, discard=bool(mode), offsets=True)
+                if con < len(w):
+                    continue
+                want = (k.tolist(), l.tolist(), offs.tolist())
+                for lane in (16, 64):
+                    cuts = hostmodel.plan_cuts(w, cert, lane)
+                    got = hostmodel.windowed(m, w, cuts[:-1], cuts[1:], lane, 7, offsets=False)
+                    if got is not None:
+                        ran += 1
+                        nonmono += not lx.info()["monotone"]
+                        disc += m.disc
+                        assert got == want[:2] + (None,), (defs, mode, lane)
+                        assert hostmodel.windowed(m, w, cuts[:-1], cuts[1:], lane, 7) == want, (defs, mode, lane)
+    assert ran > 100 and nonmono > 20 and disc > 20, (ran, nonmono, disc)
