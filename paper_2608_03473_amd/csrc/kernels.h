@@ -124,6 +124,7 @@ constexpr int kBatchMaxInst = 8;
 struct BatchInstHost {
   uint32_t start, sink, fail;
   uint32_t mono, refused;
+  uint32_t disc;  // the mode discards some kind
   CertMap cm;
 };
 struct BatchTables {
@@ -137,7 +138,8 @@ struct BatchTables {
 };
 // Workspace of a batch of ndocs documents over nbytes bytes with lane target lane_bytes.
 size_t batch_workspace_bytes(uint32_t ndocs, uint64_t nbytes, uint32_t lane_bytes);
-// LDS of the batched emit workgroup (the count walk needs less): 0 if it does not fit.
+// LDS of the batched lane-emit workgroup (the count walk needs less): 0 if it does not fit.
+// (The windowed emit takes as many waves as fit beside the table, or stands down.)
 size_t batch_emit_lds_bytes(int nrows, uint32_t ninst);
 // docs: device array of 16-byte lex_doc; res: device array of 32-byte lex_doc_result.
 hipError_t run_batch(const BatchTables &bt, const uint8_t *bytes, uint64_t nbytes, const void *docs, uint32_t ndocs,

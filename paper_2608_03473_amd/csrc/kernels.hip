@@ -1457,7 +1457,7 @@ __device__ __forceinline__ void win_tile(const Tables &tb, const WalkArgs &a, ui
   // progress ends here, as the lane walk's slice end made it (the next window starts
   // afresh and does not see it).
   st &= kRowMask;
-  if (valid && (i + 1 == nwin || next_fresh) && st != 0) {
+  if (valid && (i + 1 == nwin || next_fresh) && st != tb.start) {
     const uint32_t end = i + 1 == nwin ? a.n : (i + 1) * kWin - (uint32_t)(reinterpret_cast<uintptr_t>(a.in) & (kWin - 1));
     const uint32_t row = st >> kRowShift;
     if ((tb.info[row] & kInfoAcc) && (tb.info[row] & kInfoCount)) {
@@ -1854,6 +1854,7 @@ constexpr uint32_t kSpecWords = kSpecX / 32;
 struct BatchInst {
   uint32_t start, sink, fail;  // row byte offsets in the combined table
   uint32_t mono, refused;      // refused: empty useful map (one lane per document)
+  uint32_t disc;               // the mode discards some kind (windowed emit stages lengths)
   CertArg ca;
 };
 
@@ -1869,7 +1870,10 @@ struct DocResDev {  // mirrors lex_doc_result
   uint32_t nslices;
 };
 
-enum { kQCount = 0, kQEmit = 1, kNLanes = 2, kBad = 3, kNSpec = 4, kBatchMeta = 8 };
+// meta words: work queues (count, lane emit, windowed emit), lane / speculative-lane / tile
+// totals, a stopped batch, no windowed emit for this batch
+enum { kQCount = 0, kQEmit = 1, kNLanes = 2, kBad = 3, kNSpec = 4, kQWin = 5, kNTiles = 6, kNoWin = 7,
+       kBatchMeta = 8 };
 
 struct BatchArgs {
   const uint32_t *table;
@@ -1888,6 +1892,13 @@ struct BatchArgs {
   // per speculative lane its document, cut, last restart, and head then tail token starts
   uint32_t spec_bytes, max_spec;
   uint32_t *spec_base, *spec_fail, *spec_doc, *spec_cut, *spec_rst, *spec_bits;
+  // windowed emit: count-walk checkpoints (main slots per lane, kslots of them, and an
+  // overflow region of 64 windows per tile of each document), tiles of 64 windows per
+  // document (prefix and tile -> document map), per lane the last non-empty lane at or
+  // before it in its document, per document whether it takes the windowed emit
+  uint2 *ck_main, *ck_over;
+  uint32_t kslots, max_tiles, win_ok;  // win_ok: the combined table's rows fit a checkpoint
+  uint32_t *tile_base, *tile_doc, *lnz, *doc_win;
   uint8_t *kinds;
   uint32_t *lens;
   uint64_t *offs;
@@ -1896,8 +1907,28 @@ struct BatchArgs {
   ResultDev *total;
 };
 
+// Windows of a document of `length` bytes at address `addr`: the kWin-aligned windows of the
+// address space it touches (window 0 starts at the document's first byte), and tiles of 64.
+__device__ __forceinline__ uint32_t doc_windows(uintptr_t addr, uint32_t length) {
+  return length ? (uint32_t)(((uint64_t)length + (addr & (kWin - 1)) + kWin - 1) / kWin) : 0;
+}
+__device__ __forceinline__ uint32_t doc_tiles(uintptr_t addr, uint32_t length) {
+  return (doc_windows(addr, length) + 63) / 64;
+}
+
 __host__ __device__ inline size_t batch_lds_offset(int nrows, uint32_t ninst) {
   return align16((size_t)nrows * 1024 + 2 * (size_t)nrows + (size_t)ninst * 256);
+}
+
+// The batch windowed emit: the combined table and a stage per wave.
+__host__ __device__ inline size_t batch_win_lds_bytes(int nrows, uint32_t ninst, uint32_t waves) {
+  return batch_lds_offset(nrows, ninst) + waves * (size_t)kStageWords * 4;
+}
+// Waves of a windowed-emit workgroup: 16, 8 or 4, the most whose LDS fits; 0: none fits.
+__host__ __device__ inline uint32_t batch_win_waves(int nrows, uint32_t ninst) {
+  for (uint32_t w = 16; w >= 4; w >>= 1)
+    if (batch_win_lds_bytes(nrows, ninst, w) <= 160 * 1024) return w;
+  return 0;
 }
 
 struct BatchLds {
@@ -1977,13 +2008,14 @@ __device__ __forceinline__ void wave_range(uint32_t ndocs, uint32_t &lo, uint32_
   hi = min(ndocs, lo + per);
 }
 
-// Sums of three per-wave values over the waves before this one, and over all waves.
-__device__ __forceinline__ void wave_prefix3(const uint64_t (*wpart)[16], uint64_t pre[3], uint64_t tot[3]) {
+// Sums of Q per-wave values over the waves before this one, and over all waves.
+template <int Q>
+__device__ __forceinline__ void wave_prefix(const uint64_t (*wpart)[16], uint64_t pre[Q], uint64_t tot[Q]) {
   const uint32_t nw = blockDim.x >> 6, me = threadIdx.x >> 6;
-  for (int q = 0; q < 3; ++q) pre[q] = tot[q] = 0;
+  for (int q = 0; q < Q; ++q) pre[q] = tot[q] = 0;
   for (uint32_t w = 0; w < nw; ++w)
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
+    for (int q = 0; q < Q; ++q) {
       pre[q] += w < me ? wpart[q][w] : 0;
       tot[q] += wpart[q][w];
     }
@@ -1993,21 +2025,23 @@ __device__ __forceinline__ void wave_prefix3(const uint64_t (*wpart)[16], uint64
 // the rest, each group in document order), speculative-lane numbering, queue reset.  One pass
 // counts, one numbers.
 __global__ void __launch_bounds__(1024) k_bplan(BatchArgs a) {
-  __shared__ uint64_t wpart[3][16];  // 64-bit: a hostile table may ask for more than 2^32 lanes
+  __shared__ uint64_t wpart[4][16];  // 64-bit: a hostile table may ask for more than 2^32 lanes
   __shared__ uint32_t bad;
   const uint32_t tid = threadIdx.x, lane = tid & 63;
   const uint32_t rm = refused_mask(a);
   if (tid == 0) {
     a.meta[kQCount] = 0;
     a.meta[kQEmit] = 0;
+    a.meta[kQWin] = 0;
     bad = 0;
   }
+  const uintptr_t base = reinterpret_cast<uintptr_t>(a.bytes);
   __syncthreads();
   uint32_t lo, hi;
   wave_range(a.ndocs, lo, hi);
   // the document table is the caller's device data: a document outside the bytes, an
   // unknown instance or flag, or more lanes than the workspace holds stops the batch
-  uint64_t s_first = 0, s_rest = 0, s_spec = 0;
+  uint64_t s_first = 0, s_rest = 0, s_spec = 0, s_tiles = 0;
   bool my_bad = false;
   for (uint32_t d0 = lo; d0 < hi; d0 += 64 * kDocTiles) {
     DocDev doc[kDocTiles];
@@ -2027,6 +2061,7 @@ __global__ void __launch_bounds__(1024) k_bplan(BatchArgs a) {
         else
           s_rest += nl;
         if (spec_split(a, rm, x)) s_spec += nl;
+        if (x.offset <= a.nbytes && x.length <= a.nbytes - x.offset) s_tiles += doc_tiles(base + x.offset, x.length);
       }
     }
   }
@@ -2034,15 +2069,17 @@ __global__ void __launch_bounds__(1024) k_bplan(BatchArgs a) {
   s_first = wave_sum64(s_first);
   s_rest = wave_sum64(s_rest);
   s_spec = wave_sum64(s_spec);
+  s_tiles = wave_sum64(s_tiles);
   if (lane == 0) {
     wpart[0][tid >> 6] = s_first;
     wpart[1][tid >> 6] = s_rest;
     wpart[2][tid >> 6] = s_spec;
+    wpart[3][tid >> 6] = s_tiles;
   }
   __syncthreads();
-  uint64_t pre[3], tot[3];
-  wave_prefix3(wpart, pre, tot);
-  uint64_t r_first = pre[0], r_rest = tot[0] + pre[1], r_spec = pre[2];
+  uint64_t pre[4], tot[4];
+  wave_prefix<4>(wpart, pre, tot);
+  uint64_t r_first = pre[0], r_rest = tot[0] + pre[1], r_spec = pre[2], r_tiles = pre[3];
   for (uint32_t d0 = lo; d0 < hi; d0 += 64 * kDocTiles) {  // wave-uniform: the scans see every lane
     DocDev doc[kDocTiles];
 #pragma unroll
@@ -2055,15 +2092,20 @@ __global__ void __launch_bounds__(1024) k_bplan(BatchArgs a) {
       const uint32_t nl = in ? doc_lanes(a, rm, x) : 0;
       const bool first = nl == 1 && x.length > a.lane_bytes;
       const uint64_t vf = first ? nl : 0, vr = first ? 0 : nl, vs = in && spec_split(a, rm, x) ? nl : 0;
+      const bool fits = in && x.offset <= a.nbytes && x.length <= a.nbytes - x.offset;
+      const uint64_t vt = fits ? doc_tiles(base + x.offset, x.length) : 0;
       const uint64_t inf = wave_incl64(vf, lane), inr = wave_incl64(vr, lane), ins = wave_incl64(vs, lane);
+      const uint64_t int_ = wave_incl64(vt, lane);
       if (in) {
-        const uint64_t base = first ? r_first + inf - vf : r_rest + inr - vr;
-        a.lane_base[d] = (uint32_t)min<uint64_t>(base, 0xFFFFFFFFu);  // unused when stopped
+        const uint64_t lb = first ? r_first + inf - vf : r_rest + inr - vr;
+        a.lane_base[d] = (uint32_t)min<uint64_t>(lb, 0xFFFFFFFFu);  // unused when stopped
         a.spec_base[d] = (uint32_t)min<uint64_t>(r_spec + ins - vs, 0xFFFFFFFFu);
+        a.tile_base[d] = (uint32_t)min<uint64_t>(r_tiles + int_ - vt, 0xFFFFFFFFu);  // unused without tiles
       }
       r_first += __shfl(inf, 63);
       r_rest += __shfl(inr, 63);
       r_spec += __shfl(ins, 63);
+      r_tiles += __shfl(int_, 63);
     }
   }
   if (tid == 0) {
@@ -2072,6 +2114,11 @@ __global__ void __launch_bounds__(1024) k_bplan(BatchArgs a) {
     a.meta[kBad] = stop;
     a.meta[kNLanes] = stop ? 0 : (uint32_t)nlanes;
     a.meta[kNSpec] = stop ? 0 : (uint32_t)nspec;
+    // the windowed emit needs its checkpoints' rows in 8 bits and its tiles in the workspace
+    // (overlapping documents may ask for more tiles than the bytes hold)
+    const bool nowin = stop || !a.win_ok || tot[3] > a.max_tiles;
+    a.meta[kNoWin] = nowin;
+    a.meta[kNTiles] = nowin ? 0 : (uint32_t)tot[3];
   }
 }
 
@@ -2080,11 +2127,18 @@ __global__ void __launch_bounds__(256) k_bmap(BatchArgs a) {
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, nwaves = (gridDim.x * blockDim.x) >> 6;
   if (a.meta[kBad]) return;
+  const bool win = !a.meta[kNoWin];
+  const uintptr_t base = reinterpret_cast<uintptr_t>(a.bytes);
   for (uint32_t d = wave; d < a.ndocs; d += nwaves) {
     const uint32_t lb = a.lane_base[d], nl = a.lanes_of[d];
+    const DocDev doc = a.docs[d];
     for (uint32_t k = lane; k < nl; k += 64) a.lane_doc[lb + k] = d;
-    if (spec_split(a, refused_mask(a), a.docs[d]))
+    if (spec_split(a, refused_mask(a), doc))
       for (uint32_t k = lane; k < nl; k += 64) a.spec_doc[a.spec_base[d] + k] = d;
+    if (win) {
+      const uint32_t tb = a.tile_base[d], nt = doc_tiles(base + doc.offset, doc.length);
+      for (uint32_t k = lane; k < nt; k += 64) a.tile_doc[tb + k] = d;
+    }
   }
 }
 
@@ -2333,6 +2387,7 @@ __global__ void __launch_bounds__(256) k_bcount(BatchArgs a) {
   const BatchLds l = batch_stage(a);
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t nlanes = a.meta[kNLanes];
+  const bool ck_on = !a.meta[kNoWin];
   for (;;) {
     const uint32_t tile = next_tile(&a.meta[kQCount]);
     if ((uint64_t)tile * 64 >= nlanes) break;  // wave-uniform exit
@@ -2385,10 +2440,25 @@ __global__ void __launch_bounds__(256) k_bcount(BatchArgs a) {
     LaneState L;
     L.cnt = 0;
     Ring r{};
-    const bool halted = in.mono ? walk<false, true, false>(L, r, tb, src, doc.length, s, e)
-                                : walk<false, false, false>(L, r, tb, src, doc.length, s, e);
+    // checkpoints for the windowed emit: main slots by the window's place in the lane's
+    // nominal range, else the document's overflow region (its 64 windows per tile)
+    CkSink ck{};
+    if (ck_on) {
+      ck.base = reinterpret_cast<uintptr_t>(src);
+      ck.main = a.ck_main;
+      ck.over = a.ck_over + (size_t)a.tile_base[d] * 64;
+      ck.nlanes = a.max_lanes;
+      ck.kslots = a.kslots;
+      ck.j = j;
+      ck.jl = jj * (spec ? a.spec_bytes : a.lane_bytes);
+      ck.mis0 = (uint32_t)(ck.base & (kWin - 1));
+    }
+    const bool halted = in.mono ? walk<false, true, false, true>(L, r, tb, src, doc.length, s, e, ck)
+                                : walk<false, false, false, true>(L, r, tb, src, doc.length, s, e, ck);
     a.counts[j] = L.cnt;
-    a.halted[j] = halted;
+    // bit 0: the slice halted; bit 1: no windowed emit for its document (a fallback
+    // re-scanned positions the checkpoints describe, or counts overflow 24 bits)
+    a.halted[j] = (halted ? 1u : 0u) | ((L.fb || e - s >= (1u << 24)) ? 2u : 0u);
   }
 }
 
@@ -2398,21 +2468,35 @@ __global__ void __launch_bounds__(256) k_bdoc(BatchArgs a) {
   if (a.meta[kBad]) return;
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, nwaves = (gridDim.x * blockDim.x) >> 6;
+  const bool win = !a.meta[kNoWin];
   for (uint32_t d = wave; d < a.ndocs; d += nwaves) {
     const uint32_t lb = a.lane_base[d], nl = a.lanes_of[d];
     uint32_t run = 0, nsl = 0, halt = kNone;
+    bool nowin = !win;
+    int32_t zrun = -1;  // last non-empty lane of the earlier chunks
     for (uint32_t c = 0; c < nl; c += 64) {
       const bool ok = c + lane < nl;
       const uint32_t j = lb + c + lane;
       const uint32_t cnt = ok ? a.counts[j] : 0;
-      const bool h = ok && a.halted[j];
+      const uint32_t hf = ok ? a.halted[j] : 0;
+      const bool h = hf & 1;
       const bool ne = ok && a.cuts[j] < a.ends[j];
       uint32_t incl = cnt;
+      int32_t z = ne ? (int32_t)j : zrun;
       for (int k = 1; k < 64; k <<= 1) {
         const uint32_t v = (uint32_t)__shfl_up((int)incl, k);
-        if ((int)lane >= k) incl += v;
+        const int32_t zz = __shfl_up(z, k);
+        if ((int)lane >= k) {
+          incl += v;
+          z = max(z, zz);
+        }
       }
-      if (ok) a.lane_pre[j] = run + incl - cnt;
+      if (ok) {
+        a.lane_pre[j] = run + incl - cnt;
+        if (win) a.lnz[j] = (uint32_t)z;
+      }
+      nowin = nowin || __any(hf & 2);
+      zrun = __shfl(z, 63);
       const unsigned long long hb = __ballot(h), nb = __ballot(ne);
       if (hb) {  // wave-uniform
         const int f = __ffsll(hb) - 1;
@@ -2428,6 +2512,8 @@ __global__ void __launch_bounds__(256) k_bdoc(BatchArgs a) {
       a.doc_ntok[d] = run;
       a.doc_halt[d] = halt;
       a.doc_nsl[d] = nsl;
+      // a halted document, a fallback or a long slice: the lane emit writes it
+      a.doc_win[d] = !nowin && halt == kNone;
     }
   }
 }
@@ -2482,7 +2568,7 @@ __global__ void __launch_bounds__(1024) k_bscan(BatchArgs a) {
   }
   __syncthreads();
   uint64_t pre[3], tot[3];
-  wave_prefix3(wpart, pre, tot);
+  wave_prefix<3>(wpart, pre, tot);
   const uint64_t total = tot[0];
   const int32_t status = total > a.cap ? -4 : 0;
   uint64_t run = pre[0];
@@ -2535,7 +2621,7 @@ __global__ void __launch_bounds__(256) k_bemit(BatchArgs a) {
     if (j >= nlanes) continue;
     const uint32_t d = a.lane_doc[j];
     const uint32_t halt = a.doc_halt[d];
-    if (halt != kNone && j > halt) continue;
+    if ((halt != kNone && j > halt) || a.doc_win[d]) continue;
     const DocDev doc = a.docs[d];
     const BatchInst &in = a.inst[doc.inst];
     const uint8_t *src = a.bytes + doc.offset;
@@ -2564,6 +2650,138 @@ __global__ void __launch_bounds__(256) k_bemit(BatchArgs a) {
     }
     ring_flush_tail(r);
     if (j == halt) a.res[d].error_offset = L.tok;  // the halt offset, relative to the document
+  }
+}
+
+// The windowed emit over a batch's documents.  Work items are tiles of 64 windows of one
+// document (windows: the kWin-aligned stretches of the address space, clipped to the
+// document), taken from a queue; each wave walks one tile at a time, a window per thread,
+// from the count walk's checkpoint, stages the tile's tokens and writes them out coalesced,
+// exactly as the single-buffer windowed emit does with the document as its input (its
+// slices, cut at certified bytes or at the hybrid plan's serial token starts, are the
+// lanes; the document's end is the end of input).  Documents the count walk marked (a
+// halt, a fallback of a non-monotone automaton, a slice of 2^24 bytes or more) are left to
+// the lane emit.
+// A document's windowed-emit context (wave-uniform).
+struct BDoc {
+  const uint8_t *src;
+  uint32_t len, mis0, nwin, lb, nl, lnom, out0, lim;
+  const uint2 *over;
+  uint32_t inst;
+};
+
+// First-round loads for window i of the document (the candidate owner's slice and the last
+// non-empty lane before it; all three addresses are known without a load).
+struct BWinR1 {
+  uint32_t ws, j0, s0, e0, lz;
+};
+
+__device__ __forceinline__ BWinR1 bwin_r1(const BatchArgs &a, const BDoc &c, uint32_t i) {
+  BWinR1 r{};
+  if (i >= c.nwin) return r;
+  r.ws = i ? i * kWin - c.mis0 : 0;  // document-relative start
+  r.j0 = c.lb + min(r.ws / c.lnom, c.nl - 1);
+  r.s0 = a.cuts[r.j0];
+  r.e0 = a.ends[r.j0];
+  r.lz = r.j0 > c.lb ? a.lnz[r.j0 - 1] : r.j0;  // lane 0 starts at 0: it owns a window it misses
+  return r;
+}
+
+// Second round: the owner's state at the window's start and its first output slot.  Past the
+// document's windows: the document's output end.
+__device__ __forceinline__ WinMeta bwin_meta(const BatchArgs &a, const BDoc &c, const BatchInst &in,
+                                             const BWinR1 &r, uint32_t i) {
+  WinMeta m{0, 0, c.lim, 0};
+  if (i >= c.nwin) return m;
+  const bool here = r.s0 < r.e0 && r.s0 <= r.ws;
+  const uint32_t j = here ? r.j0 : r.lz;
+  const uint32_t base = c.out0 + a.lane_pre[j];
+  if (here && r.s0 == r.ws) {  // the lane starts here: a fresh token
+    m.st = in.start;
+    m.tok = r.ws;
+    m.out = base;
+    m.fresh = 1;
+    return m;
+  }
+  const uint32_t k = (r.ws - (j - c.lb) * c.lnom) / kWin;
+  const uint2 ck = k < a.kslots ? a.ck_main[ck_index(k, j, a.max_lanes)] : c.over[i];
+  m.st = row_state(ck.x >> 24);
+  m.tok = ck.y;
+  m.out = base + (ck.x & 0xFFFFFFu);
+  return m;
+}
+
+// Each wave takes a contiguous range of tiles (no queue: a device-scope atomic per tile
+// costs more than the tile) and walks it document segment by document segment; within a
+// segment the next tile's bytes and the following tiles' window states load while a tile
+// walks, as in the single-buffer windowed emit.
+__global__ void __launch_bounds__(1024) k_bemit_win(BatchArgs a) {
+  if (a.meta[kNoWin] || a.total->status != 0) return;  // uniform: no barrier follows
+  const BatchLds l = batch_stage(a);
+  const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6, wpb = blockDim.x >> 6;
+  uint32_t *stage = reinterpret_cast<uint32_t *>(l.ring) + wid * kStageWords;
+  const uint32_t ntiles = a.meta[kNTiles];
+  const uint32_t rm = refused_mask(a);
+  const uint32_t nwaves = gridDim.x * wpb, gw = blockIdx.x * wpb + wid;
+  const uint32_t per = (ntiles + nwaves - 1) / nwaves;
+  const uint32_t t_lo = min(ntiles, gw * per), t_hi = min(ntiles, t_lo + per);
+  for (uint32_t t = t_lo; t < t_hi;) {
+    const uint32_t d = a.tile_doc[t];
+    const DocDev doc = a.docs[d];
+    const uint32_t tb0 = a.tile_base[d];
+    BDoc c;
+    c.src = a.bytes + doc.offset;
+    c.len = doc.length;
+    c.mis0 = (uint32_t)(reinterpret_cast<uintptr_t>(c.src) & (kWin - 1));
+    c.nwin = doc_windows(reinterpret_cast<uintptr_t>(c.src), doc.length);
+    const uint32_t nt = (c.nwin + 63) / 64;
+    const uint32_t tt_lo = t - tb0, tt_hi = min(t_hi, tb0 + nt) - tb0;
+    t = tb0 + tt_hi;  // the next segment
+    if (!a.doc_win[d]) continue;
+    c.lb = a.lane_base[d];
+    c.nl = a.lanes_of[d];
+    c.lnom = spec_split(a, rm, doc) ? a.spec_bytes : a.lane_bytes;
+    c.out0 = (uint32_t)a.res[d].tok_offset;
+    c.lim = c.out0 + (uint32_t)a.res[d].ntokens;  // the document's outputs end here
+    c.over = a.ck_over + (size_t)tb0 * 64;
+    c.inst = doc.inst;
+    const BatchInst &in = a.inst[doc.inst];
+    const Tables tb{l.T, l.info, l.kind, in.sink, in.fail, in.start};
+    WalkArgs wa{};
+    wa.in = c.src;
+    wa.n = c.len;
+    wa.kinds = a.kinds;
+    wa.lens = a.lens;
+    wa.offs = a.offs;
+    auto wpos = [&](uint32_t tt) { return (int64_t)(tt * 64 + lane) * kWin - c.mis0; };
+    auto is_edge = [&](uint32_t tt) { return tt == 0 || tt + 1 == nt; };
+    WinMeta cur = bwin_meta(a, c, in, bwin_r1(a, c, tt_lo * 64 + lane), tt_lo * 64 + lane);
+    WinMeta nxt = bwin_meta(a, c, in, bwin_r1(a, c, (tt_lo + 1) * 64 + lane), (tt_lo + 1) * 64 + lane);
+    BWinR1 r1 = bwin_r1(a, c, (tt_lo + 2) * 64 + lane);
+    Win64 dat = is_edge(tt_lo) ? win_load<true>(c.src, wpos(tt_lo), c.len) : win_load<false>(c.src, wpos(tt_lo), c.len);
+    for (uint32_t tt = tt_lo; tt < tt_hi; ++tt) {
+      const uint32_t i = tt * 64 + lane;
+      Win64 ndat = dat;
+      if (tt + 1 < tt_hi)
+        ndat = is_edge(tt + 1) ? win_load<true>(c.src, wpos(tt + 1), c.len)
+                               : win_load<false>(c.src, wpos(tt + 1), c.len);
+      const WinMeta n2 = bwin_meta(a, c, in, r1, (tt + 2) * 64 + lane);
+      r1 = bwin_r1(a, c, (tt + 3) * 64 + lane);
+      const uint32_t o_first = __shfl(cur.out, 0), o_next = __shfl(nxt.out, 0);
+      const uint32_t down = __shfl_down(cur.out, 1), fdown = __shfl_down(cur.fresh, 1);
+      const uint32_t f_next = __shfl(nxt.fresh, 0);
+      const uint32_t P = __shfl(cur.tok, 0);
+      const uint32_t span_end = (uint32_t)min<int64_t>((int64_t)(tt + 1) * 64 * kWin - c.mis0, c.len);
+      if (in.disc)
+        win_tile<true>(tb, wa, stage, lane, cur, i, i < c.nwin, is_edge(tt), dat, wpos(tt), c.nwin, o_first, o_next,
+                       true, lane < 63 ? down : o_next, lane < 63 ? fdown : f_next, P, span_end, c.lim);
+      else
+        win_tile<false>(tb, wa, stage, lane, cur, i, i < c.nwin, is_edge(tt), dat, wpos(tt), c.nwin, o_first, o_next,
+                        true, lane < 63 ? down : o_next, lane < 63 ? fdown : f_next, P, span_end, c.lim);
+      cur = nxt;
+      nxt = n2;
+      dat = ndat;
+    }
   }
 }
 
@@ -2899,11 +3117,19 @@ static uint32_t batch_max_spec(uint32_t ndocs, uint64_t nbytes, uint32_t lane_by
   return (uint32_t)std::min<uint64_t>(0xFFFFFFF0ull, (uint64_t)ndocs + nbytes / batch_spec_bytes(lane_bytes) + 1);
 }
 
+// tiles of 64 windows: a document of n bytes touches at most n / kWin + 2 windows
+static uint32_t batch_max_tiles(uint32_t ndocs, uint64_t nbytes) {
+  return (uint32_t)std::min<uint64_t>(0xFFFFFFF0ull, 2ull * ndocs + nbytes / (64 * kWin) + 1);
+}
+
 size_t batch_workspace_bytes(uint32_t ndocs, uint64_t nbytes, uint32_t lane_bytes) {
   const uint64_t nl = batch_max_lanes(ndocs, nbytes, lane_bytes);
   const uint64_t ns = batch_max_spec(ndocs, nbytes, lane_bytes);
-  return align256(kBatchMeta * 4) + 7 * align256((size_t)std::max<uint32_t>(ndocs, 1) * 4) +
-         6 * align256((size_t)nl * 4) + 3 * align256((size_t)ns * 4) + align256((size_t)ns * 2 * kSpecWords * 4);
+  const uint64_t nt = batch_max_tiles(ndocs, nbytes);
+  const size_t per_doc = align256((size_t)std::max<uint32_t>(ndocs, 1) * 4);
+  return align256(kBatchMeta * 4) + 9 * per_doc + 7 * align256((size_t)nl * 4) + 3 * align256((size_t)ns * 4) +
+         align256((size_t)ns * 2 * kSpecWords * 4) + align256((size_t)ck_slots(lane_bytes) * nl * 8) +
+         align256((size_t)nt * 64 * 8) + align256((size_t)nt * 4);
 }
 
 size_t batch_emit_lds_bytes(int nrows, uint32_t ninst) {
@@ -2930,6 +3156,7 @@ hipError_t run_batch(const BatchTables &bt, const uint8_t *bytes, uint64_t nbyte
     a.inst[k].fail = bt.inst[k].fail;
     a.inst[k].mono = bt.inst[k].mono;
     a.inst[k].refused = bt.inst[k].refused;
+    a.inst[k].disc = bt.inst[k].disc;
     a.inst[k].ca = cert_arg(bt.inst[k].cm);
   }
   a.bytes = bytes;
@@ -2950,6 +3177,8 @@ hipError_t run_batch(const BatchTables &bt, const uint8_t *bytes, uint64_t nbyte
   a.doc_nsl = reinterpret_cast<uint32_t *>(w), w += dsz;
   a.spec_base = reinterpret_cast<uint32_t *>(w), w += dsz;
   a.spec_fail = reinterpret_cast<uint32_t *>(w), w += dsz;
+  a.tile_base = reinterpret_cast<uint32_t *>(w), w += dsz;
+  a.doc_win = reinterpret_cast<uint32_t *>(w), w += dsz;
   a.spec_bytes = batch_spec_bytes(lane_bytes);
   a.max_spec = batch_max_spec(ndocs, nbytes, lane_bytes);
   const size_t per_spec = align256((size_t)a.max_spec * 4);
@@ -2964,6 +3193,15 @@ hipError_t run_batch(const BatchTables &bt, const uint8_t *bytes, uint64_t nbyte
   a.counts = reinterpret_cast<uint32_t *>(w), w += per_lane;
   a.halted = reinterpret_cast<uint32_t *>(w), w += per_lane;
   a.lane_pre = reinterpret_cast<uint32_t *>(w), w += per_lane;
+  a.lnz = reinterpret_cast<uint32_t *>(w), w += per_lane;
+  // windowed emit: checkpoints (main slots per lane, overflow per document tile), tile map
+  a.kslots = ck_slots(lane_bytes);
+  a.max_tiles = batch_max_tiles(ndocs, nbytes);
+  a.ck_main = reinterpret_cast<uint2 *>(w), w += align256((size_t)a.kslots * a.max_lanes * 8);
+  a.ck_over = reinterpret_cast<uint2 *>(w), w += align256((size_t)a.max_tiles * 64 * 8);
+  a.tile_doc = reinterpret_cast<uint32_t *>(w), w += align256((size_t)a.max_tiles * 4);
+  const uint32_t win_waves = batch_win_waves(bt.nrows, bt.ninst);
+  a.win_ok = bt.nrows <= 256 && win_waves;  // checkpoints keep the row in 8 bits
   a.kinds = kinds;
   a.lens = lens;
   a.offs = offs;
@@ -3006,8 +3244,13 @@ hipError_t run_batch(const BatchTables &bt, const uint8_t *bytes, uint64_t nbyte
     e = hipGetLastError();
   }
   mark(ev, 3, s);
-  if (e == hipSuccess) {
+  if (e == hipSuccess) {  // the lane emit: documents the windowed emit does not take
     k_bemit<<<(uint32_t)cus * per_cu_e, 256, lds_e, s>>>(a);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess && win_waves) {  // the windowed emit: 16 waves per CU as LDS allows
+    k_bemit_win<<<(uint32_t)cus * (16 / win_waves), win_waves * 64, batch_win_lds_bytes(bt.nrows, bt.ninst, win_waves),
+                  s>>>(a);
     e = hipGetLastError();
   }
   mark(ev, 4, s);

@@ -528,6 +528,7 @@ int lex_batch_create(const lex_dfa *const *dfas, const int32_t *modes, uint32_t 
     in.fail = c.row_fail >= 0 ? state(base + (uint32_t)c.row_fail) : in.sink;
     in.mono = c.monotone ? 1 : 0;
     in.refused = dfas[k]->cm[m].nbytes == 0;
+    in.disc = dfas[k]->all_counted[m] ? 0 : 1;
     in.cm = dfas[k]->cm[m];
     base += (uint32_t)c.nrows;
   }
