@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=4.0, help="per arrival rate (plus 1 s warm-up)")
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the 1 MiB, 256 MiB JSON and stray-byte configuration legs")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="time the library's default configuration instead of the autotuner's choice")
+    ap.add_argument("--tune-cache", default=os.path.join("/tmp", "lexgpu_tune.json"))
     ap.add_argument("--only", choices=["framed"], default=None,
                     help="run that leg alone (no headline scan): for kernel traces and counters")
     ap.add_argument("--cpu-threads", type=int, default=0,
@@ -88,6 +91,18 @@ def main():
     lx = P.Lexer.compile(T.as_tuples(T.CLIKE_L))
     mode = P.LEX_MODE_EXACT
     opts = P.RunOpts(chunk_bytes=args.chunk_bytes, lane_bytes=args.lane_bytes, path=args.path)
+    tuning = None
+    if not args.no_tune and not args.lane_bytes and not args.path:
+        # the autotuner's configuration for this token set, mode, device and size (measured
+        # here, every candidate checked against the defaults' output)
+        from paper_2608_03473_amd import tune
+        tu = tune.Tuner(cache_path=args.tune_cache)
+        e = tu.tune(lx, data, mode, args.chunk_bytes, force=True)
+        opts = tune.opts_of(e["opts"])
+        tuning = {"choice": e["opts"], "plan": e["plan"], "ms": round(e["ms"], 4),
+                  "default_ms": round(e["default_ms"], 4), "candidates": len(e["candidates"]),
+                  "timing": "HIP events, median of 5 scans per candidate"}
+        log(args, f"tuning: {tuning}")
     cap = n
     kinds = torch.empty(cap, dtype=torch.uint8, device=dev)
     lens = torch.empty(cap, dtype=torch.int32, device=dev)
@@ -117,7 +132,8 @@ def main():
     evs = [PhaseEvents() for _ in range(args.steps)]
     step_opts = []
     for e in evs:
-        o = P.RunOpts(chunk_bytes=args.chunk_bytes, lane_bytes=args.lane_bytes, path=args.path)
+        o = P.RunOpts(chunk_bytes=opts.chunk_bytes, lane_bytes=opts.lane_bytes, path=opts.path,
+                      block_threads=opts.block_threads, emit=opts.emit)
         o.events = e.array
         step_opts.append(o)
     torch.cuda.synchronize()
@@ -169,11 +185,12 @@ def main():
         "tokens_per_s": round(ntok / (ms * 1e-3), 1),
         "path_roofline_frac": round(path_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "parity": parity,
+        "tuning": tuning,
         "phase_ms": {k: round(float(v), 4) for k, v in zip(names, ph_mean)},
         "roofline": {
             "bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(dom, n, args.lane_bytes, args.path),
+            "traffic": measured_traffic(dom, n, opts.lane_bytes, opts.path),
             "algorithmic_bytes_per_launch": int(algo[dom]),
             "timing": "HIP events on the scan's stream at the phase boundaries, over a second pass of the "
                       "same steps right after the timed one (each event record adds about 3 us to a step)",
@@ -373,18 +390,27 @@ def batched_leg(args):
     docs = np.zeros(nd, dtype=P.DOC_DTYPE)
     docs["offset"], docs["length"], docs["inst"] = offs, sizes, sets
     docs_dev = torch.from_numpy(docs.view(np.uint8).copy()).to(dev)
+    bopts, btune = None, None
+    if not args.no_tune:
+        from paper_2608_03473_amd import tune
+        tu = tune.Tuner(cache_path=args.tune_cache)
+        e = tu.tune_batch(batch, [(lx, m) for lx, (_, m) in zip(lexers, insts)], data, docs_dev, nd, force=True)
+        bopts = tune.opts_of(e["opts"])
+        btune = {"choice": e["opts"], "ms": round(e["ms"], 3), "default_ms": round(e["default_ms"], 3),
+                 "candidates": [(c["opts"].get("lane_bytes", 0), round(c["ms"], 3)) for c in e["candidates"]]}
+        log(args, f"batch tuning: {btune}")
     kinds = torch.empty(n, dtype=torch.uint8, device=dev)
     lens = torch.empty(n, dtype=torch.int32, device=dev)
     res = torch.empty(nd * 32, dtype=torch.uint8, device=dev)
     total = torch.zeros(3, dtype=torch.int64, device=dev)
-    ws = torch.empty(batch.workspace_size(nd, n), dtype=torch.uint8, device=dev)
+    ws = torch.empty(batch.workspace_size(nd, n, bopts), dtype=torch.uint8, device=dev)
     stream = torch.cuda.current_stream()
     for _ in range(2):
-        batch.run_into(data, n, docs_dev, nd, kinds, lens, None, n, res, total, ws, stream=stream)
+        batch.run_into(data, n, docs_dev, nd, kinds, lens, None, n, res, total, ws, bopts, stream=stream)
     torch.cuda.synchronize()
     t = time.perf_counter()
     for _ in range(args.batch_steps):
-        batch.run_into(data, n, docs_dev, nd, kinds, lens, None, n, res, total, ws, stream=stream)
+        batch.run_into(data, n, docs_dev, nd, kinds, lens, None, n, res, total, ws, bopts, stream=stream)
     torch.cuda.synchronize()
     t_batch = (time.perf_counter() - t) / args.batch_steps
     tot = total.cpu().numpy()
@@ -408,7 +434,7 @@ def batched_leg(args):
     side.wait_stream(stream)
     with torch.cuda.stream(side):
         with torch.cuda.graph(g, stream=side):
-            batch.run_into(data, n, docs_dev, nd, kinds, lens, None, n, res, total, ws,
+            batch.run_into(data, n, docs_dev, nd, kinds, lens, None, n, res, total, ws, bopts,
                            stream=torch.cuda.current_stream())
     torch.cuda.synchronize()
     for _ in range(2):
@@ -430,6 +456,7 @@ def batched_leg(args):
         "graph_same_tokens": graph_same,
         "roofline_frac": round((n + 5 * ntok_batch) / min(t_batch, t_graph) / 1e9 / HBM_PEAK_GBS, 4),
         "parity": par,
+        "tuning": btune,
     }
     if args.batch_only:
         return head

@@ -1871,9 +1871,9 @@ struct DocResDev {  // mirrors lex_doc_result
 };
 
 // meta words: work queues (count, lane emit, windowed emit), lane / speculative-lane / tile
-// totals, a stopped batch, no windowed emit for this batch
+// totals, a stopped batch, no windowed emit for this batch, some document for the lane emit
 enum { kQCount = 0, kQEmit = 1, kNLanes = 2, kBad = 3, kNSpec = 4, kQWin = 5, kNTiles = 6, kNoWin = 7,
-       kBatchMeta = 8 };
+       kAnyLane = 8, kBatchMeta = 16 };
 
 struct BatchArgs {
   const uint32_t *table;
@@ -2033,6 +2033,7 @@ __global__ void __launch_bounds__(1024) k_bplan(BatchArgs a) {
     a.meta[kQCount] = 0;
     a.meta[kQEmit] = 0;
     a.meta[kQWin] = 0;
+    a.meta[kAnyLane] = 0;
     bad = 0;
   }
   const uintptr_t base = reinterpret_cast<uintptr_t>(a.bytes);
@@ -2469,6 +2470,7 @@ __global__ void __launch_bounds__(256) k_bdoc(BatchArgs a) {
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, nwaves = (gridDim.x * blockDim.x) >> 6;
   const bool win = !a.meta[kNoWin];
+  bool any_lane = false;  // some document of this wave's takes the lane emit
   for (uint32_t d = wave; d < a.ndocs; d += nwaves) {
     const uint32_t lb = a.lane_base[d], nl = a.lanes_of[d];
     uint32_t run = 0, nsl = 0, halt = kNone;
@@ -2513,9 +2515,12 @@ __global__ void __launch_bounds__(256) k_bdoc(BatchArgs a) {
       a.doc_halt[d] = halt;
       a.doc_nsl[d] = nsl;
       // a halted document, a fallback or a long slice: the lane emit writes it
-      a.doc_win[d] = !nowin && halt == kNone;
+      const bool w = !nowin && halt == kNone;
+      a.doc_win[d] = w;
+      any_lane |= !w;
     }
   }
+  if (lane == 0 && any_lane) a.meta[kAnyLane] = 1;  // every writer stores the same value
 }
 
 // One workgroup: output offsets of the documents (exclusive scan), results, status.
@@ -2610,6 +2615,7 @@ __global__ void __launch_bounds__(1024) k_bscan(BatchArgs a) {
 
 // Emit walk of the batch: the lane emit of each lane up to its document's first halted one.
 __global__ void __launch_bounds__(256) k_bemit(BatchArgs a) {
+  if (!a.meta[kAnyLane]) return;  // every document takes the windowed emit (uniform)
   const BatchLds l = batch_stage(a);
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t nlanes = a.meta[kNLanes];

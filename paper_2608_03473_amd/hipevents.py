@@ -25,6 +25,7 @@ def _lib():
         _hip.hipEventDestroy.argtypes = [C.c_void_p]
         _hip.hipEventSynchronize.argtypes = [C.c_void_p]
         _hip.hipEventElapsedTime.argtypes = [C.POINTER(C.c_float), C.c_void_p, C.c_void_p]
+        _hip.hipEventRecord.argtypes = [C.c_void_p, C.c_void_p]
     return _hip
 
 
@@ -71,3 +72,25 @@ class PhaseEvents:
             self.close()
         except Exception:
             pass
+
+
+class StreamTimer:
+    """Times work enqueued on a HIP stream (passed as its handle) between two events."""
+
+    def __init__(self):
+        self.ev = PhaseEvents(2)
+
+    def __enter__(self):
+        return self
+
+    def start(self, stream_handle):
+        _lib().hipEventRecord(self.ev.ev[0], C.c_void_p(stream_handle))
+
+    def stop(self, stream_handle) -> None:
+        _lib().hipEventRecord(self.ev.ev[1], C.c_void_p(stream_handle))
+
+    def ms(self) -> float:
+        return self.ev.elapsed_ms()[0]
+
+    def __exit__(self, *exc):
+        self.ev.close()
