@@ -1033,7 +1033,7 @@ __device__ __forceinline__ CkSink ck_sink(const WalkArgs &a, uint32_t j) {
   return ck;
 }
 
-// CK: record checkpoints for the windowed emit (monotone automata only).
+// CK: record checkpoints for the windowed emit.
 template <bool MONO, bool FUSED, bool CK>
 __global__ void __launch_bounds__(1024) k_count(WalkArgs a) {
   const Lds l = carve_lds(a.nrows);
@@ -1436,9 +1436,11 @@ __device__ __forceinline__ void win_tile(const Tables &tb, const WalkArgs &a, ui
   w.tok = cur.tok;
   uint32_t d0 = 0;
   if (staged) {
-    // spill words: the stage's first 64; slots follow, so 0 < D < 4 * kStageWords
-    w.G = stage_addr + 4 * lane;
-    w.D = d0 = 4 * (64 - lane + pad + (cur.out - o_first));
+    // the spill word: one for the whole wave (the stage's first word; 64 are reserved), so
+    // the lanes whose step ends no token all write one address and take no LDS bank from a
+    // lane writing a slot; slots follow, so 0 < D < 4 * kStageWords
+    w.G = stage_addr;
+    w.D = d0 = 4 * (64 + pad + (cur.out - o_first));
     w.base = P;
     if (lane == 0) stage[64 + pad - 1] = 0;
     if (valid) {
