@@ -33,7 +33,8 @@ def parse():
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--lane-bytes", type=int, default=0)
     ap.add_argument("--chunk-bytes", type=int, default=64 << 10)
-    ap.add_argument("--path", type=int, default=0, help="0 default, 1 pipeline, 2 fused")
+    ap.add_argument("--path", type=int, default=0, help="0 default, 1 pipeline, 2 fused, 3 one pass")
+    ap.add_argument("--block-threads", type=int, default=0, help="threads per walk workgroup (0: default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle CPU time")
     ap.add_argument("--quiet", action="store_true")
@@ -90,9 +91,10 @@ def main():
     data = torch.from_numpy(host).to(dev)
     lx = P.Lexer.compile(T.as_tuples(T.CLIKE_L))
     mode = P.LEX_MODE_EXACT
-    opts = P.RunOpts(chunk_bytes=args.chunk_bytes, lane_bytes=args.lane_bytes, path=args.path)
+    opts = P.RunOpts(chunk_bytes=args.chunk_bytes, lane_bytes=args.lane_bytes, path=args.path,
+                     block_threads=args.block_threads)
     tuning = None
-    if not args.no_tune and not args.lane_bytes and not args.path:
+    if not args.no_tune and not args.lane_bytes and not args.path and not args.block_threads:
         # the autotuner's configuration for this token set, mode, device and size (measured
         # here, every candidate checked against the defaults' output)
         from paper_2608_03473_amd import tune
@@ -103,6 +105,8 @@ def main():
                   "default_ms": round(e["default_ms"], 4), "candidates": len(e["candidates"]),
                   "timing": "HIP events, median of 5 scans per candidate"}
         log(args, f"tuning: {tuning}")
+        for c in sorted(e["candidates"], key=lambda c: c["ms"]):
+            log(args, f"  candidate {c['ms']:.4f} ms {c['plan']} emit={c['opts'].get('emit', 0)}")
     cap = n
     kinds = torch.empty(cap, dtype=torch.uint8, device=dev)
     lens = torch.empty(cap, dtype=torch.int32, device=dev)
@@ -457,6 +461,7 @@ def batched_leg(args):
         "roofline_frac": round((n + 5 * ntok_batch) / min(t_batch, t_graph) / 1e9 / HBM_PEAK_GBS, 4),
         "parity": par,
         "tuning": btune,
+        "workspace_mib": round(ws.numel() / 2**20, 1),
     }
     if args.batch_only:
         return head

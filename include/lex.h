@@ -116,7 +116,8 @@ int lex_compile_framed(const lex_tokdef *defs, uint32_t ndefs, uint32_t reserved
 int lex_compile_table(int32_t nstates, int32_t q0, const int32_t *next, const int32_t *accept,
                       const uint8_t *discard, int32_t ntok, lex_dfa **out, char *err, size_t errlen);
 
-/* Releases a lexer (host and device tables).  The caller must not have scans in flight. */
+/* Releases a lexer (host and device tables).  Resource management, no operation of the
+ * paper.  The caller must not have scans in flight. */
 void lex_free(lex_dfa *dfa);
 
 /* Useful certified set of a mode (host call): bits[b >> 3] bit (b & 7) is set iff byte b is
@@ -125,10 +126,19 @@ void lex_free(lex_dfa *dfa);
  * (vacuous bytes included).  LEX_MODE_SERIAL returns the empty set. */
 int lex_cert(const lex_dfa *dfa, int mode, int raw, uint8_t bits[32]);
 
+/* Summary of the compiled automaton (host call, into *out): its kinds, the states of the
+ * trimmed and minimised live automaton (Section 4.1) and its byte classes, whether q0 is
+ * re-entrant (Definition 1), whether it is monotone (no live edge from an accepting to a
+ * non-accepting state: longest match then never falls back, Section 3) and whether q0 is
+ * live at all.  Returns LEX_EINVAL for null arguments. */
 int lex_info(const lex_dfa *dfa, lex_info_t *out);
 
-/* Host copy of the packed table of a mode: nrows*256 u32 entries (layout documented in
- * the library source) and nrows row-info bytes; for host-side models in tests. */
+/* Host copy of the packed transition table of a mode: the longest-match DFA of Section 3,
+ * trimmed and minimised (Section 4.1), one u32 per (row, byte) holding the next row, the
+ * accepting and token-end flags of the step and the kind it emits (layout documented in
+ * the library source), plus nrows row-info and row-kind bytes.  Caller-owned host arrays of
+ * at least nrows*256 and nrows entries (LEX_ELIMIT otherwise; NULL skips an array); for
+ * host-side models and the autotuner's table digest. */
 int lex_tables(const lex_dfa *dfa, int mode, uint32_t *table, size_t table_entries,
                uint8_t *rowinfo, uint8_t *rowkind, size_t nrows);
 
@@ -168,7 +178,8 @@ typedef struct {
 } lex_run_opts;
 
 /* The configuration lex_run would use for n bytes in this mode under opts (NULL =
- * defaults): for tools and benchmarks that attribute time and bytes to kernels.  path is
+ * defaults): no operation of the paper; for tools, the autotuner and benchmarks that
+ * attribute time and bytes to kernels.  path is
  * 1, 2 or 3 as in lex_run_opts (never 0); windowed: the windowed emit applies; hybrid: the
  * hybrid plan splits a refused set (path is then 1: its count walk, scan and emit run on
  * the speculative cuts, lane_bytes is the speculative lane).  Returns what lex_run would
@@ -182,7 +193,8 @@ typedef struct {
 } lex_plan_info;
 int lex_plan(const lex_dfa *dfa, uint64_t n, int mode, const lex_run_opts *opts, lex_plan_info *out);
 
-/* Device workspace bytes lex_run needs for n input bytes under opts (NULL = defaults). */
+/* Device workspace bytes lex_run needs for n input bytes under opts (NULL = defaults):
+ * memory sizing, no operation of the paper.  0 for arguments lex_run would refuse. */
 size_t lex_workspace_size(const lex_dfa *dfa, uint64_t n, int mode, const lex_run_opts *opts);
 
 /* Scans d_bytes[0, n) (device pointer) and writes, on `stream`, at most cap tokens:
