@@ -1875,7 +1875,7 @@ struct DocResDev {  // mirrors lex_doc_result
 // meta words: work queues (count, lane emit, windowed emit), lane / speculative-lane / tile
 // totals, a stopped batch, no windowed emit for this batch, some document for the lane emit
 enum { kQCount = 0, kQEmit = 1, kNLanes = 2, kBad = 3, kNSpec = 4, kQWin = 5, kNTiles = 6, kNoWin = 7,
-       kAnyLane = 8, kBatchMeta = 16 };
+       kAnyLane = 8, kQCount2 = 9, kBatchMeta = 16 };
 
 struct BatchArgs {
   const uint32_t *table;
@@ -1888,6 +1888,7 @@ struct BatchArgs {
   const DocDev *docs;
   uint32_t ndocs, lane_bytes, max_lanes;
   uint32_t *meta;  // kBatchMeta words: queues, lane count
+  uint64_t *part;  // kDocGroups x kPartWords: per-group sums of the planning and result kernels
   uint32_t *lanes_of, *lane_base, *lane_doc, *cuts, *ends, *counts, *halted, *lane_pre, *doc_halt;
   uint32_t *doc_ntok, *doc_nsl;
   // hybrid plan: per document the first speculative lane's index and the fall-back flag;
@@ -1982,13 +1983,24 @@ __device__ __forceinline__ uint32_t doc_lanes(const BatchArgs &a, uint32_t rm, c
   return one_lane(a, rm, d) ? 1 : ceil_div(d.length, a.lane_bytes);
 }
 
-// The single-workgroup kernels (k_bplan, k_bscan) give each wave a contiguous range of
-// documents and walk it 64 documents at a time, one per lane, so every load is coalesced
-// (one CU serves the whole table: a per-thread range would touch 64 lines per instruction
-// and overflow its L1).  kDocTiles tiles are loaded before any is used, unconditionally from
-// an index clamped into the range (a guarded load compiles to a branch that waits on it);
-// lanes past the range then drop what they loaded.
-constexpr uint32_t kDocTiles = 4;
+// The planning and result kernels (k_bplan_*, k_bscan_*) split the document table into at
+// most kDocGroups contiguous groups, one workgroup of 256 threads each, a document per
+// thread at a time (coalesced loads).  A first kernel writes each group's sums to part[],
+// a second adds the earlier groups' sums (every workgroup reads all of them) and scans its
+// own documents.  (One workgroup for the whole table left the chip idle for 0.2 ms at
+// 50 000 documents.)
+constexpr uint32_t kDocGroups = 256;
+constexpr uint32_t kPartWords = 8;  // per group: plan sums (0-4), result sums (5-7)
+
+__host__ __device__ inline uint32_t doc_groups(uint32_t ndocs) {
+  return ndocs > 256u * kDocGroups ? kDocGroups : ndocs ? (ndocs + 255) / 256 : 1;
+}
+
+__device__ __forceinline__ void group_range(uint32_t ndocs, uint32_t &lo, uint32_t &hi) {
+  const uint32_t per = (ndocs + gridDim.x - 1) / gridDim.x;
+  lo = min(ndocs, blockIdx.x * per);
+  hi = min(ndocs, lo + per);
+}
 
 __device__ __forceinline__ uint64_t wave_sum64(uint64_t v) {
   for (int k = 32; k; k >>= 1) v += __shfl_xor(v, k);
@@ -2003,117 +2015,136 @@ __device__ __forceinline__ uint64_t wave_incl64(uint64_t v, uint32_t lane) {
   return v;
 }
 
-// Contiguous document range of one wave of a single-workgroup kernel.
-__device__ __forceinline__ void wave_range(uint32_t ndocs, uint32_t &lo, uint32_t &hi) {
-  const uint32_t nw = blockDim.x >> 6, per = (ndocs + nw - 1) / nw;
-  lo = min(ndocs, (threadIdx.x >> 6) * per);
-  hi = min(ndocs, lo + per);
-}
-
-// Sums of Q per-wave values over the waves before this one, and over all waves.
+// Sums of Q values over the workgroup (256 threads); red: Q x 4 words of LDS.
 template <int Q>
-__device__ __forceinline__ void wave_prefix(const uint64_t (*wpart)[16], uint64_t pre[Q], uint64_t tot[Q]) {
-  const uint32_t nw = blockDim.x >> 6, me = threadIdx.x >> 6;
-  for (int q = 0; q < Q; ++q) pre[q] = tot[q] = 0;
-  for (uint32_t w = 0; w < nw; ++w)
+__device__ __forceinline__ void block_sum(uint64_t (&v)[Q], uint64_t (*red)[4]) {
+  const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      pre[q] += w < me ? wpart[q][w] : 0;
-      tot[q] += wpart[q][w];
-    }
+  for (int q = 0; q < Q; ++q) v[q] = wave_sum64(v[q]);
+  if (lane == 0)
+#pragma unroll
+    for (int q = 0; q < Q; ++q) red[q][wid] = v[q];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < Q; ++q) v[q] = red[q][0] + red[q][1] + red[q][2] + red[q][3];
+  __syncthreads();
 }
 
-// One workgroup: lanes per document, lane numbering (long single-lane documents first, then
-// the rest, each group in document order), speculative-lane numbering, queue reset.  One pass
-// counts, one numbers.
-__global__ void __launch_bounds__(1024) k_bplan(BatchArgs a) {
-  __shared__ uint64_t wpart[4][16];  // 64-bit: a hostile table may ask for more than 2^32 lanes
-  __shared__ uint32_t bad;
-  const uint32_t tid = threadIdx.x, lane = tid & 63;
+// Inclusive scan of Q values over the workgroup (256 threads), and their totals.
+template <int Q>
+__device__ __forceinline__ void block_incl(uint64_t (&v)[Q], uint64_t (&tot)[Q], uint64_t (*red)[4]) {
+  const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) v[q] = wave_incl64(v[q], lane);
+  if (lane == 63)
+#pragma unroll
+    for (int q = 0; q < Q; ++q) red[q][wid] = v[q];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    uint64_t pre = 0, t = 0;
+    for (uint32_t w = 0; w < 4; ++w) {
+      pre += w < wid ? red[q][w] : 0;
+      t += red[q][w];
+    }
+    v[q] += pre;
+    tot[q] = t;
+  }
+  __syncthreads();
+}
+
+// Sums of words [q0, q0 + Q) of part[] over the groups before this one (pre) and over all
+// groups (tot).
+template <int Q>
+__device__ __forceinline__ void group_prefix(const uint64_t *part, uint32_t q0, uint64_t (&pre)[Q],
+                                             uint64_t (&tot)[Q], uint64_t (*red)[4]) {
+  const uint32_t t = threadIdx.x;
+  uint64_t v[2 * Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const uint64_t x = t < gridDim.x ? part[(size_t)t * kPartWords + q0 + q] : 0;
+    v[q] = t < blockIdx.x ? x : 0;
+    v[Q + q] = x;
+  }
+  block_sum<2 * Q>(v, red);
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    pre[q] = v[q];
+    tot[q] = v[Q + q];
+  }
+}
+
+// Planning, first half: lanes per document, each group's lane, speculative-lane and tile
+// sums and whether it holds a bad record; the queues reset.  The document table is the
+// caller's device data: a document outside the bytes, an unknown instance or flag, or more
+// lanes than the workspace holds stops the batch.
+__global__ void __launch_bounds__(256) k_bplan_a(BatchArgs a) {
+  __shared__ uint64_t red[5][4];
   const uint32_t rm = refused_mask(a);
-  if (tid == 0) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
     a.meta[kQCount] = 0;
+    a.meta[kQCount2] = 0;
     a.meta[kQEmit] = 0;
     a.meta[kQWin] = 0;
     a.meta[kAnyLane] = 0;
-    bad = 0;
   }
   const uintptr_t base = reinterpret_cast<uintptr_t>(a.bytes);
-  __syncthreads();
   uint32_t lo, hi;
-  wave_range(a.ndocs, lo, hi);
-  // the document table is the caller's device data: a document outside the bytes, an
-  // unknown instance or flag, or more lanes than the workspace holds stops the batch
-  uint64_t s_first = 0, s_rest = 0, s_spec = 0, s_tiles = 0;
-  bool my_bad = false;
-  for (uint32_t d0 = lo; d0 < hi; d0 += 64 * kDocTiles) {
-    DocDev doc[kDocTiles];
-#pragma unroll
-    for (uint32_t u = 0; u < kDocTiles; ++u) doc[u] = a.docs[min(d0 + u * 64 + lane, hi - 1)];
-#pragma unroll
-    for (uint32_t u = 0; u < kDocTiles; ++u) {
-      const uint32_t d = d0 + u * 64 + lane;
-      if (d < hi) {
-        const DocDev &x = doc[u];
-        my_bad |= x.offset > a.nbytes || x.length > a.nbytes - x.offset || x.inst >= a.ninst || x.flags > 1;
-        const uint32_t nl = doc_lanes(a, rm, x);
-        a.lanes_of[d] = nl;
-        a.spec_fail[d] = 0;
-        if (nl == 1 && x.length > a.lane_bytes)
-          s_first += nl;
-        else
-          s_rest += nl;
-        if (spec_split(a, rm, x)) s_spec += nl;
-        if (x.offset <= a.nbytes && x.length <= a.nbytes - x.offset) s_tiles += doc_tiles(base + x.offset, x.length);
-      }
+  group_range(a.ndocs, lo, hi);
+  uint64_t v[5] = {0, 0, 0, 0, 0};  // single-lane long documents, other lanes, speculative lanes, tiles, bad
+  for (uint32_t d = lo + threadIdx.x; d < hi; d += blockDim.x) {
+    const DocDev x = a.docs[d];
+    const bool fits = x.offset <= a.nbytes && x.length <= a.nbytes - x.offset;
+    v[4] |= !fits || x.inst >= a.ninst || x.flags > 1;
+    const uint32_t nl = doc_lanes(a, rm, x);
+    a.lanes_of[d] = nl;
+    a.spec_fail[d] = 0;
+    const bool first = nl == 1 && x.length > a.lane_bytes;
+    v[0] += first ? nl : 0;
+    v[1] += first ? 0 : nl;
+    if (spec_split(a, rm, x)) v[2] += nl;
+    if (fits) v[3] += doc_tiles(base + x.offset, x.length);
+  }
+  block_sum<5>(v, red);
+  if (threadIdx.x < 5) a.part[(size_t)blockIdx.x * kPartWords + threadIdx.x] = v[threadIdx.x];
+}
+
+// Planning, second half: lane numbering (long single-lane documents first, then the rest,
+// each in document order), speculative-lane and tile numbering; the first group writes the
+// totals and the stop flags.
+__global__ void __launch_bounds__(256) k_bplan_b(BatchArgs a) {
+  __shared__ uint64_t red[10][4];
+  const uint32_t rm = refused_mask(a);
+  const uintptr_t base = reinterpret_cast<uintptr_t>(a.bytes);
+  uint64_t pre[5], tot[5];
+  group_prefix<5>(a.part, 0, pre, tot, red);
+  uint64_t r[4] = {pre[0], tot[0] + pre[1], pre[2], pre[3]};  // 64-bit: a hostile table may ask for 2^32 lanes
+  uint32_t lo, hi;
+  group_range(a.ndocs, lo, hi);
+  for (uint32_t d0 = lo; d0 < hi; d0 += blockDim.x) {  // workgroup-uniform: the scans see every thread
+    const uint32_t d = d0 + threadIdx.x;
+    const bool in = d < hi;
+    const DocDev x = a.docs[in ? d : lo];
+    const uint32_t nl = in ? a.lanes_of[d] : 0;
+    const bool first = nl == 1 && x.length > a.lane_bytes;
+    const bool fits = in && x.offset <= a.nbytes && x.length <= a.nbytes - x.offset;
+    uint64_t v[4] = {first ? nl : 0, first ? 0 : nl, in && spec_split(a, rm, x) ? nl : 0,
+                     fits ? doc_tiles(base + x.offset, x.length) : 0};
+    const uint64_t v0[4] = {v[0], v[1], v[2], v[3]};
+    uint64_t t[4];
+    block_incl<4>(v, t, red);
+    if (in) {
+      const uint64_t lb = first ? r[0] + v[0] - v0[0] : r[1] + v[1] - v0[1];
+      a.lane_base[d] = (uint32_t)min<uint64_t>(lb, 0xFFFFFFFFu);  // unused when stopped
+      a.spec_base[d] = (uint32_t)min<uint64_t>(r[2] + v[2] - v0[2], 0xFFFFFFFFu);
+      a.tile_base[d] = (uint32_t)min<uint64_t>(r[3] + v[3] - v0[3], 0xFFFFFFFFu);  // unused without tiles
     }
-  }
-  if (my_bad) atomicOr(&bad, 1u);
-  s_first = wave_sum64(s_first);
-  s_rest = wave_sum64(s_rest);
-  s_spec = wave_sum64(s_spec);
-  s_tiles = wave_sum64(s_tiles);
-  if (lane == 0) {
-    wpart[0][tid >> 6] = s_first;
-    wpart[1][tid >> 6] = s_rest;
-    wpart[2][tid >> 6] = s_spec;
-    wpart[3][tid >> 6] = s_tiles;
-  }
-  __syncthreads();
-  uint64_t pre[4], tot[4];
-  wave_prefix<4>(wpart, pre, tot);
-  uint64_t r_first = pre[0], r_rest = tot[0] + pre[1], r_spec = pre[2], r_tiles = pre[3];
-  for (uint32_t d0 = lo; d0 < hi; d0 += 64 * kDocTiles) {  // wave-uniform: the scans see every lane
-    DocDev doc[kDocTiles];
 #pragma unroll
-    for (uint32_t u = 0; u < kDocTiles; ++u) doc[u] = a.docs[min(d0 + u * 64 + lane, hi - 1)];
-#pragma unroll
-    for (uint32_t u = 0; u < kDocTiles; ++u) {
-      const uint32_t d = d0 + u * 64 + lane;
-      const bool in = d < hi;
-      const DocDev &x = doc[u];
-      const uint32_t nl = in ? doc_lanes(a, rm, x) : 0;
-      const bool first = nl == 1 && x.length > a.lane_bytes;
-      const uint64_t vf = first ? nl : 0, vr = first ? 0 : nl, vs = in && spec_split(a, rm, x) ? nl : 0;
-      const bool fits = in && x.offset <= a.nbytes && x.length <= a.nbytes - x.offset;
-      const uint64_t vt = fits ? doc_tiles(base + x.offset, x.length) : 0;
-      const uint64_t inf = wave_incl64(vf, lane), inr = wave_incl64(vr, lane), ins = wave_incl64(vs, lane);
-      const uint64_t int_ = wave_incl64(vt, lane);
-      if (in) {
-        const uint64_t lb = first ? r_first + inf - vf : r_rest + inr - vr;
-        a.lane_base[d] = (uint32_t)min<uint64_t>(lb, 0xFFFFFFFFu);  // unused when stopped
-        a.spec_base[d] = (uint32_t)min<uint64_t>(r_spec + ins - vs, 0xFFFFFFFFu);
-        a.tile_base[d] = (uint32_t)min<uint64_t>(r_tiles + int_ - vt, 0xFFFFFFFFu);  // unused without tiles
-      }
-      r_first += __shfl(inf, 63);
-      r_rest += __shfl(inr, 63);
-      r_spec += __shfl(ins, 63);
-      r_tiles += __shfl(int_, 63);
-    }
+    for (int q = 0; q < 4; ++q) r[q] += t[q];
   }
-  if (tid == 0) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
     const uint64_t nlanes = tot[0] + tot[1], nspec = tot[2];
-    const bool stop = bad || nlanes > a.max_lanes || nspec > a.max_spec;
+    const bool stop = tot[4] || nlanes > a.max_lanes || nspec > a.max_spec;
     a.meta[kBad] = stop;
     a.meta[kNLanes] = stop ? 0 : (uint32_t)nlanes;
     a.meta[kNSpec] = stop ? 0 : (uint32_t)nspec;
@@ -2179,6 +2210,14 @@ __device__ void walk_spec(const Tables &tb, const uint8_t *in, uint32_t n, uint3
   const uintptr_t base = reinterpret_cast<uintptr_t>(in);
   int64_t cb = INT64_MIN;  // position of the cached block (16-aligned in memory)
   uint4 cv = make_uint4(0, 0, 0, 0);
+  // Aligned blocks are loaded four ahead of the walk (a speculative walk runs at a few
+  // waves per CU, so nothing else hides a load's latency): q0..q3 hold the blocks at qp,
+  // qp + 16, qp + 32, qp + 48.  A load past the last aligned block that fits reads that
+  // block instead (n >= 32 here), and its bytes are never walked.
+  const int64_t qlast = (int64_t)(((base + n - 16) & ~(uintptr_t)15) - base);
+  auto qload = [&](int64_t x) { return *reinterpret_cast<const uint4 *>(in + min(x, qlast)); };
+  int64_t qp = INT64_MIN;
+  uint4 q0 = cv, q1 = cv, q2 = cv, q3 = cv;
   // the token starts of one aligned 16-byte block (bit k: position P + k) into both bitmaps,
   // a word at a time (positions come in increasing order, as for mark)
   auto mark_bits = [&](uint32_t mk, uint32_t P) {
@@ -2220,7 +2259,18 @@ __device__ void walk_spec(const Tables &tb, const uint8_t *in, uint32_t n, uint3
       // an aligned block without cursors: 16 steps, their EMIT and ACC bits as masks (bit
       // 16 + k: step k); a halt or FAIL inside leaves the row there, flagless, to the
       // block's end, and the restart below acts on it as after the step that caused it
-      const uint4 v = *reinterpret_cast<const uint4 *>(in + p);
+      if (qp != (int64_t)p) {
+        q0 = qload(p);
+        q1 = qload((int64_t)p + 16);
+        q2 = qload((int64_t)p + 32);
+        q3 = qload((int64_t)p + 48);
+      }
+      const uint4 v = q0;
+      q0 = q1;
+      q1 = q2;
+      q2 = q3;
+      q3 = qload((int64_t)p + 64);
+      qp = (int64_t)p + 16;
       uint32_t e = st, me = 0, ma = 0;
       const uint32_t st0 = st;
 #pragma unroll
@@ -2323,27 +2373,22 @@ __device__ void walk_spec(const Tables &tb, const uint8_t *in, uint32_t n, uint3
   tail[tw] = tv;
 }
 
-// Speculative walks: one thread per speculative lane.
-__global__ void __launch_bounds__(256) k_bspec(BatchArgs a) {
-  const BatchLds l = batch_stage(a);
-  if (a.meta[kBad]) return;
-  const uint32_t ns = a.meta[kNSpec];
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < ns; i += gridDim.x * blockDim.x) {
-    const uint32_t d = a.spec_doc[i];
-    const DocDev doc = a.docs[d];
-    const BatchInst &in = a.inst[doc.inst];
-    const uint32_t k = i - a.spec_base[d], S = a.spec_bytes;
-    const uint32_t b = k * S;  // < length
-    // the tail window; past the document's end it can hold no token start
-    const uint32_t b2 = (uint32_t)min<uint64_t>((uint64_t)(k + 1) * S, doc.length);
-    const uint32_t end = (uint32_t)min<uint64_t>((uint64_t)b2 + kSpecX, doc.length);
-    const Tables tb{l.T, l.info, l.kind, in.sink, in.fail, in.start};
-    uint32_t *bits = a.spec_bits + (size_t)i * 2 * kSpecWords;
-    uint32_t rst;
-    if (in.mono) walk_spec<true>(tb, a.bytes + doc.offset, doc.length, b, end, b2, bits, bits + kSpecWords, rst);
-    else walk_spec<false>(tb, a.bytes + doc.offset, doc.length, b, end, b2, bits, bits + kSpecWords, rst);
-    a.spec_rst[i] = rst;
-  }
+// The speculative walk of speculative lane i (< the batch's count of them).
+__device__ __forceinline__ void spec_lane(const BatchArgs &a, const BatchLds &l, uint32_t i) {
+  const uint32_t d = a.spec_doc[i];
+  const DocDev doc = a.docs[d];
+  const BatchInst &in = a.inst[doc.inst];
+  const uint32_t k = i - a.spec_base[d], S = a.spec_bytes;
+  const uint32_t b = k * S;  // < length
+  // the tail window; past the document's end it can hold no token start
+  const uint32_t b2 = (uint32_t)min<uint64_t>((uint64_t)(k + 1) * S, doc.length);
+  const uint32_t end = (uint32_t)min<uint64_t>((uint64_t)b2 + kSpecX, doc.length);
+  const Tables tb{l.T, l.info, l.kind, in.sink, in.fail, in.start};
+  uint32_t *bits = a.spec_bits + (size_t)i * 2 * kSpecWords;
+  uint32_t rst;
+  if (in.mono) walk_spec<true>(tb, a.bytes + doc.offset, doc.length, b, end, b2, bits, bits + kSpecWords, rst);
+  else walk_spec<false>(tb, a.bytes + doc.offset, doc.length, b, end, b2, bits, bits + kSpecWords, rst);
+  a.spec_rst[i] = rst;
 }
 
 // Cuts of the hybrid plan: one thread per speculative lane k; lane k's cut is the first
@@ -2385,17 +2430,39 @@ __device__ __forceinline__ uint32_t next_tile(uint32_t *q) {
 }
 
 // Count walk of the batch: each lane places its own slice inside its document (the fused
-// planner) and counts it with its document's table.
+// planner) and counts it with its document's table.  Two passes around the hybrid plan's
+// cuts.  PASS 1 takes tiles from one queue: first the speculative lanes' walks (few and
+// serial, they would leave the chip idle in a launch of their own), then the lanes of every
+// document that is not split by the hybrid plan, which keep the chip busy meanwhile.
+// PASS 2, after the cuts, counts the split documents' lanes, taken through the
+// speculative lanes' numbering (a split document's lanes are its speculative lanes).
+template <int PASS>
 __global__ void __launch_bounds__(256) k_bcount(BatchArgs a) {
   const BatchLds l = batch_stage(a);
   const uint32_t lane = threadIdx.x & 63;
-  const uint32_t nlanes = a.meta[kNLanes];
+  const uint32_t nlanes = a.meta[kNLanes], nspec = a.meta[kNSpec];
+  const uint32_t nst = PASS == 1 ? (nspec + 63) / 64 : 0;  // speculative tiles first
   const bool ck_on = !a.meta[kNoWin];
   for (;;) {
-    const uint32_t tile = next_tile(&a.meta[kQCount]);
-    if ((uint64_t)tile * 64 >= nlanes) break;  // wave-uniform exit
-    const uint32_t j = tile * 64 + lane;
-    const bool valid = j < nlanes;
+    const uint32_t tile = next_tile(&a.meta[PASS == 1 ? kQCount : kQCount2]);
+    if (PASS == 1 && tile < nst) {  // wave-uniform
+      const uint32_t i = tile * 64 + lane;
+      if (i < nspec) spec_lane(a, l, i);
+      continue;
+    }
+    const uint32_t t = tile - nst;
+    if ((uint64_t)t * 64 >= (PASS == 1 ? nlanes : nspec)) break;  // wave-uniform exit
+    bool valid;
+    uint32_t j;
+    if (PASS == 1) {
+      j = t * 64 + lane;
+      valid = j < nlanes;
+    } else {
+      const uint32_t i = t * 64 + lane;
+      valid = i < nspec;
+      const uint32_t ds = valid ? a.spec_doc[i] : 0;
+      j = valid ? a.lane_base[ds] + (i - a.spec_base[ds]) : 0;
+    }
     uint32_t d = 0, jj = 0, nl = 1, start = kNone;
     DocDev doc{0, 0, 0, 0};
     if (valid) {
@@ -2414,7 +2481,7 @@ __global__ void __launch_bounds__(256) k_bcount(BatchArgs a) {
     }
     // the next lane's start, when that lane is this document's and this tile's
     const uint32_t nstart = (uint32_t)__shfl_down((int)start, 1);
-    if (!valid) continue;
+    if (!valid || (PASS == 1 && spec)) continue;
     const bool same = lane < 63 && jj + 1 < nl;
     uint32_t s, e;
     if (spec) {  // the hybrid plan's slice, or the whole document on one lane
@@ -2525,11 +2592,30 @@ __global__ void __launch_bounds__(256) k_bdoc(BatchArgs a) {
   if (lane == 0 && any_lane) a.meta[kAnyLane] = 1;  // every writer stores the same value
 }
 
-// One workgroup: output offsets of the documents (exclusive scan), results, status.
-__global__ void __launch_bounds__(1024) k_bscan(BatchArgs a) {
+// Results, first half: each group's token, halted-document and slice sums.
+__global__ void __launch_bounds__(256) k_bscan_a(BatchArgs a) {
+  __shared__ uint64_t red[3][4];
+  if (a.meta[kBad]) return;  // uniform: no barrier follows
+  uint32_t lo, hi;
+  group_range(a.ndocs, lo, hi);
+  uint64_t v[3] = {0, 0, 0};
+  for (uint32_t d = lo + threadIdx.x; d < hi; d += blockDim.x) {
+    v[0] += a.doc_ntok[d];
+    v[1] += a.doc_halt[d] != kNone;
+    v[2] += a.doc_nsl[d];
+  }
+  block_sum<3>(v, red);
+  if (threadIdx.x < 3) a.part[(size_t)blockIdx.x * kPartWords + 5 + threadIdx.x] = v[threadIdx.x];
+}
+
+// Results, second half: output offsets of the documents (exclusive scan), results, status;
+// the first group writes the batch's totals.
+__global__ void __launch_bounds__(256) k_bscan_b(BatchArgs a) {
+  __shared__ uint64_t red[6][4];
   if (a.meta[kBad]) {  // nothing was counted: report the bad table
-    for (uint32_t d = threadIdx.x; d < a.ndocs; d += blockDim.x) a.res[d] = DocResDev{0, 0, 0, -1, 0};
-    if (threadIdx.x == 0) {
+    for (uint32_t d = blockIdx.x * blockDim.x + threadIdx.x; d < a.ndocs; d += gridDim.x * blockDim.x)
+      a.res[d] = DocResDev{0, 0, 0, -1, 0};
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
       a.total->ntokens = 0;
       a.total->error_offset = 0;
       a.total->status = -1;
@@ -2537,77 +2623,31 @@ __global__ void __launch_bounds__(1024) k_bscan(BatchArgs a) {
     }
     return;
   }
-  __shared__ uint64_t wpart[3][16];
-  const uint32_t tid = threadIdx.x, lane = tid & 63;
-  uint32_t lo, hi;
-  wave_range(a.ndocs, lo, hi);
-  uint64_t sum = 0, nerr = 0, nsl = 0;
-  for (uint32_t d0 = lo; d0 < hi; d0 += 64 * kDocTiles) {
-    uint32_t nt_[kDocTiles], h_[kDocTiles], ns_[kDocTiles];
-#pragma unroll
-    for (uint32_t u = 0; u < kDocTiles; ++u) {
-      const uint32_t dc = min(d0 + u * 64 + lane, hi - 1);
-      nt_[u] = a.doc_ntok[dc];
-      h_[u] = a.doc_halt[dc];
-      ns_[u] = a.doc_nsl[dc];
-    }
-#pragma unroll
-    for (uint32_t u = 0; u < kDocTiles; ++u)
-      if (d0 + u * 64 + lane >= hi) {
-        nt_[u] = 0;
-        h_[u] = kNone;
-        ns_[u] = 0;
-      }
-#pragma unroll
-    for (uint32_t u = 0; u < kDocTiles; ++u) {
-      sum += nt_[u];
-      nerr += h_[u] != kNone;
-      nsl += ns_[u];
-    }
-  }
-  sum = wave_sum64(sum);
-  nerr = wave_sum64(nerr);
-  nsl = wave_sum64(nsl);
-  if (lane == 0) {
-    wpart[0][tid >> 6] = sum;
-    wpart[1][tid >> 6] = nerr;
-    wpart[2][tid >> 6] = nsl;
-  }
-  __syncthreads();
   uint64_t pre[3], tot[3];
-  wave_prefix<3>(wpart, pre, tot);
+  group_prefix<3>(a.part, 5, pre, tot, red);
   const uint64_t total = tot[0];
   const int32_t status = total > a.cap ? -4 : 0;
   uint64_t run = pre[0];
-  for (uint32_t d0 = lo; d0 < hi; d0 += 64 * kDocTiles) {  // wave-uniform: the scans see every lane
-    uint32_t nt_[kDocTiles], ns_[kDocTiles], len_[kDocTiles];
-#pragma unroll
-    for (uint32_t u = 0; u < kDocTiles; ++u) {
-      const uint32_t dc = min(d0 + u * 64 + lane, hi - 1);
-      nt_[u] = a.doc_ntok[dc];
-      ns_[u] = a.doc_nsl[dc];
-      len_[u] = a.docs[dc].length;
+  uint32_t lo, hi;
+  group_range(a.ndocs, lo, hi);
+  for (uint32_t d0 = lo; d0 < hi; d0 += blockDim.x) {  // workgroup-uniform: the scan sees every thread
+    const uint32_t d = d0 + threadIdx.x;
+    const bool in = d < hi;
+    const uint32_t nt = in ? a.doc_ntok[d] : 0;
+    uint64_t v[1] = {nt}, t[1];
+    block_incl<1>(v, t, red);
+    if (in) {
+      DocResDev r;
+      r.tok_offset = run + v[0] - nt;
+      r.ntokens = nt;
+      r.error_offset = a.docs[d].length;  // a halted document's emit replaces it
+      r.status = status;
+      r.nslices = a.doc_nsl[d];
+      a.res[d] = r;
     }
-#pragma unroll
-    for (uint32_t u = 0; u < kDocTiles; ++u)
-      if (d0 + u * 64 + lane >= hi) nt_[u] = 0;  // the scan adds nothing past the range
-#pragma unroll
-    for (uint32_t u = 0; u < kDocTiles; ++u) {
-      const uint32_t d = d0 + u * 64 + lane;
-      const uint64_t incl = wave_incl64(nt_[u], lane);
-      if (d < hi) {
-        DocResDev r;
-        r.tok_offset = run + incl - nt_[u];
-        r.ntokens = nt_[u];
-        r.error_offset = len_[u];  // a halted document's emit replaces it
-        r.status = status;
-        r.nslices = ns_[u];
-        a.res[d] = r;
-      }
-      run += __shfl(incl, 63);
-    }
+    run += t[0];
   }
-  if (tid == 0) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
     a.total->ntokens = total;
     a.total->error_offset = tot[1];  // documents that did not tokenize completely
     a.total->status = status;
@@ -3135,7 +3175,7 @@ size_t batch_workspace_bytes(uint32_t ndocs, uint64_t nbytes, uint32_t lane_byte
   const uint64_t ns = batch_max_spec(ndocs, nbytes, lane_bytes);
   const uint64_t nt = batch_max_tiles(ndocs, nbytes);
   const size_t per_doc = align256((size_t)std::max<uint32_t>(ndocs, 1) * 4);
-  return align256(kBatchMeta * 4) + 9 * per_doc + 7 * align256((size_t)nl * 4) + 3 * align256((size_t)ns * 4) +
+  return align256(kBatchMeta * 4) + align256((size_t)kDocGroups * kPartWords * 8) + 9 * per_doc + 7 * align256((size_t)nl * 4) + 3 * align256((size_t)ns * 4) +
          align256((size_t)ns * 2 * kSpecWords * 4) + align256((size_t)ck_slots(lane_bytes) * nl * 8) +
          align256((size_t)nt * 64 * 8) + align256((size_t)nt * 4);
 }
@@ -3177,6 +3217,8 @@ hipError_t run_batch(const BatchTables &bt, const uint8_t *bytes, uint64_t nbyte
   uint8_t *w = static_cast<uint8_t *>(ws);
   a.meta = reinterpret_cast<uint32_t *>(w);
   w += align256(kBatchMeta * 4);
+  a.part = reinterpret_cast<uint64_t *>(w);
+  w += align256((size_t)kDocGroups * kPartWords * 8);
   const size_t dsz = align256((size_t)std::max<uint32_t>(ndocs, 1) * 4);
   a.lanes_of = reinterpret_cast<uint32_t *>(w), w += dsz;
   a.lane_base = reinterpret_cast<uint32_t *>(w), w += dsz;
@@ -3222,24 +3264,29 @@ hipError_t run_batch(const BatchTables &bt, const uint8_t *bytes, uint64_t nbyte
   const uint32_t per_cu_c = (uint32_t)std::min<size_t>(8, 160 * 1024 / lds_c);
   const uint32_t per_cu_e = (uint32_t)std::min<size_t>(8, 160 * 1024 / lds_e);
   const uint32_t gdoc = std::max<uint32_t>(1, std::min<uint32_t>(4096, (ndocs + 3) / 4));
+  const uint32_t ngroups = doc_groups(ndocs);
   mark(ev, 0, s);
-  k_bplan<<<1, 1024, 0, s>>>(a);
+  k_bplan_a<<<ngroups, 256, 0, s>>>(a);
   hipError_t e = hipGetLastError();
+  if (e == hipSuccess) {
+    k_bplan_b<<<ngroups, 256, 0, s>>>(a);
+    e = hipGetLastError();
+  }
   if (e == hipSuccess) {
     k_bmap<<<gdoc, 256, 0, s>>>(a);
     e = hipGetLastError();
   }
-  if (e == hipSuccess) {  // the hybrid plan's speculative walks and cuts
-    k_bspec<<<(uint32_t)cus * per_cu_c, 256, lds_c, s>>>(a);
+  mark(ev, 1, s);
+  if (e == hipSuccess) {  // speculative walks, then the lanes of documents not split by them
+    k_bcount<1><<<(uint32_t)cus * per_cu_c, 256, lds_c, s>>>(a);
     e = hipGetLastError();
   }
-  if (e == hipSuccess) {
+  if (e == hipSuccess) {  // the hybrid plan's cuts
     k_bsync<<<(uint32_t)cus * 4, 256, 0, s>>>(a);
     e = hipGetLastError();
   }
-  mark(ev, 1, s);
-  if (e == hipSuccess) {
-    k_bcount<<<(uint32_t)cus * per_cu_c, 256, lds_c, s>>>(a);
+  if (e == hipSuccess) {  // the lanes of the split documents
+    k_bcount<2><<<(uint32_t)cus * per_cu_c, 256, lds_c, s>>>(a);
     e = hipGetLastError();
   }
   mark(ev, 2, s);
@@ -3248,7 +3295,11 @@ hipError_t run_batch(const BatchTables &bt, const uint8_t *bytes, uint64_t nbyte
     e = hipGetLastError();
   }
   if (e == hipSuccess) {
-    k_bscan<<<1, 1024, 0, s>>>(a);
+    k_bscan_a<<<ngroups, 256, 0, s>>>(a);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) {
+    k_bscan_b<<<ngroups, 256, 0, s>>>(a);
     e = hipGetLastError();
   }
   mark(ev, 3, s);

@@ -90,7 +90,7 @@ def test_windowed_emit_model():
             cuts = hostmodel.plan_cuts(w, cert, lane)
             plans = [(cuts[:-1], cuts[1:]), hostmodel.plan_fused(w, cert, lane)]
             for starts, ends in plans:
-                for base in (0, 3, 63):
+                for base in (0, 3, 63, 64, 100):
                     for stage in (1280, 150):
                         got = hostmodel.windowed(m, w, starts, ends, lane, base, 4, stage)
                         assert got == want, (name, lane, base, stage)
@@ -223,7 +223,7 @@ def test_windowed_emit_model_nonmonotone():
             for lane in (64, 1024):
                 cuts = hostmodel.plan_cuts(w, cert, lane)
                 for starts, ends in [(cuts[:-1], cuts[1:]), hostmodel.plan_fused(w, cert, lane)]:
-                    for base in (0, 5):
+                    for base in (0, 5, 70):
                         assert hostmodel.windowed(m, w, starts, ends, lane, base, 4, 1280) == want, lane
                         got = hostmodel.windowed(m, w, starts, ends, lane, base, 4, 1280, offsets=False)
                         assert got == want[:2] + (None,), (mode, lane)
