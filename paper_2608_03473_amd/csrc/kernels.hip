@@ -2540,18 +2540,41 @@ __global__ void __launch_bounds__(256) k_bdoc(BatchArgs a) {
   const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, nwaves = (gridDim.x * blockDim.x) >> 6;
   const bool win = !a.meta[kNoWin];
   bool any_lane = false;  // some document of this wave's takes the lane emit
+  // the next document's lane range and the next chunk's lanes load while the current ones
+  // are scanned (a document of thousands of lanes would otherwise wait on every chunk)
+  uint32_t n_lb = 0, n_nl = 1;
+  if (wave < a.ndocs) {
+    n_lb = a.lane_base[wave];
+    n_nl = a.lanes_of[wave];
+  }
   for (uint32_t d = wave; d < a.ndocs; d += nwaves) {
-    const uint32_t lb = a.lane_base[d], nl = a.lanes_of[d];
+    const uint32_t lb = n_lb, nl = n_nl;  // nl >= 1
+    if (d + nwaves < a.ndocs) {
+      n_lb = a.lane_base[d + nwaves];
+      n_nl = a.lanes_of[d + nwaves];
+    }
     uint32_t run = 0, nsl = 0, halt = kNone;
     bool nowin = !win;
     int32_t zrun = -1;  // last non-empty lane of the earlier chunks
+    // lanes past the document's last reload that lane (any defined value does)
+    auto load = [&](uint32_t c, uint32_t &cn, uint32_t &hf, uint32_t &cu, uint32_t &en) {
+      const uint32_t jc = lb + min(c + lane, nl - 1);
+      cn = a.counts[jc];
+      hf = a.halted[jc];
+      cu = a.cuts[jc];
+      en = a.ends[jc];
+    };
+    uint32_t q_cn, q_hf, q_cu, q_en;
+    load(0, q_cn, q_hf, q_cu, q_en);
     for (uint32_t c = 0; c < nl; c += 64) {
+      const uint32_t cn0 = q_cn, hf0 = q_hf, cu0 = q_cu, en0 = q_en;
+      if (c + 64 < nl) load(c + 64, q_cn, q_hf, q_cu, q_en);  // wave-uniform
       const bool ok = c + lane < nl;
       const uint32_t j = lb + c + lane;
-      const uint32_t cnt = ok ? a.counts[j] : 0;
-      const uint32_t hf = ok ? a.halted[j] : 0;
+      const uint32_t cnt = ok ? cn0 : 0;
+      const uint32_t hf = ok ? hf0 : 0;
       const bool h = hf & 1;
-      const bool ne = ok && a.cuts[j] < a.ends[j];
+      const bool ne = ok && cu0 < en0;
       uint32_t incl = cnt;
       int32_t z = ne ? (int32_t)j : zrun;
       for (int k = 1; k < 64; k <<= 1) {
