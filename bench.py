@@ -21,7 +21,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 MANIFEST_DIR = os.path.join(ROOT, "tests", "golden")  # the oracle's whole-stream digests
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2608_03473_amd", "csrc", "kernels.hip")
-HBM_SUMMARY = os.path.join(ROOT, "profiles", "onepass_clike512_hbm.md")
+PROFILES = os.path.join(ROOT, "profiles")  # *_hbm.md: counter summaries of the scan's kernels
 
 
 def parse():
@@ -194,7 +194,7 @@ def main():
         "roofline": {
             "bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(dom, n, opts.lane_bytes, opts.path),
+            "traffic": measured_traffic(dom, n, plan),
             "algorithmic_bytes_per_launch": int(algo[dom]),
             "timing": "HIP events on the scan's stream at the phase boundaries, over a second pass of the "
                       "same steps right after the timed one (each event record adds about 3 us to a step)",
@@ -623,27 +623,30 @@ def code_digest(path):
     return hashlib.sha256(" ".join(src.split()).encode()).hexdigest()
 
 
-def measured_traffic(kernel, n, lane_bytes, path):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary
-    (FETCH_SIZE and WRITE_SIZE, scaled against a plain copy), or None when the summary was
-    taken on other kernel code or another workload."""
-    try:
-        sha = code_digest(KERNEL_SOURCE)
+def measured_traffic(kernel, n, plan):
+    """HBM bytes per launch of the phase `kernel` from a committed rocprofv3 counter summary
+    (profiles/*_hbm.md: FETCH_SIZE and WRITE_SIZE, scaled against a plain copy) taken on the
+    same kernel code, workload size and resolved plan (path, lane length, workgroup size), or
+    None when there is none."""
+    import glob
+
+    sha = code_digest(KERNEL_SOURCE)
+    want = {"kernels_hip_code_sha256": sha, "workload_n": str(n), "path": str(plan["path"]),
+            "lane_bytes": str(plan["lane_bytes"]), "block_threads": str(plan["block_threads"])}
+    for path in sorted(glob.glob(os.path.join(PROFILES, "*_hbm.md"))):
         fields = {}
-        with open(HBM_SUMMARY) as f:
-            for line in f:
-                if ":" in line and not line.startswith(("|", "#", " ")):
-                    k, v = line.split(":", 1)
-                    fields[k.strip()] = v.strip()
-    except OSError:
-        return None
-    if fields.get("kernels_hip_code_sha256") != sha:
-        return None
-    if fields.get("workload_n") != str(n) or fields.get("lane_bytes") != str(lane_bytes or "auto") \
-            or fields.get("path") != str(path or "default"):
-        return None
-    v = fields.get(f"traffic_bytes_{kernel}")
-    return int(v) if v else None
+        try:
+            with open(path, encoding="utf-8") as f:
+                for line in f:
+                    if ":" in line and not line.startswith(("|", "#", " ", "(")):
+                        k, v = line.split(":", 1)
+                        fields[k.strip()] = v.strip()
+        except OSError:
+            continue
+        if all(fields.get(k) == v for k, v in want.items()):
+            v = fields.get(f"traffic_bytes_{kernel}")
+            return int(v) if v else None
+    return None
 
 
 def cpu_baseline(host, args):

@@ -2437,7 +2437,7 @@ __device__ __forceinline__ uint32_t next_tile(uint32_t *q) {
 // PASS 2, after the cuts, counts the split documents' lanes, taken through the
 // speculative lanes' numbering (a split document's lanes are its speculative lanes).
 template <int PASS>
-__global__ void __launch_bounds__(256) k_bcount(BatchArgs a) {
+__global__ void __launch_bounds__(1024) k_bcount(BatchArgs a) {
   const BatchLds l = batch_stage(a);
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t nlanes = a.meta[kNLanes], nspec = a.meta[kNSpec];
@@ -3284,7 +3284,12 @@ hipError_t run_batch(const BatchTables &bt, const uint8_t *bytes, uint64_t nbyte
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   const size_t lds_c = batch_lds_offset(bt.nrows, bt.ninst);
-  const uint32_t per_cu_c = (uint32_t)std::min<size_t>(8, 160 * 1024 / lds_c);
+  // the first count pass: workgroups of 16 waves, so that one copy of the combined table in
+  // LDS serves the four waves per SIMD the kernel's registers allow (workgroups of 4 waves,
+  // each with its own copy, ran out of LDS at three per CU when the table is large); the
+  // second, a few serial walks, spreads them over more CUs in workgroups of 4 waves
+  const uint32_t per_cu_c = (uint32_t)std::max<size_t>(1, std::min<size_t>(2, 160 * 1024 / lds_c));
+  const uint32_t per_cu_c4 = (uint32_t)std::min<size_t>(8, 160 * 1024 / lds_c);
   const uint32_t per_cu_e = (uint32_t)std::min<size_t>(8, 160 * 1024 / lds_e);
   const uint32_t gdoc = std::max<uint32_t>(1, std::min<uint32_t>(4096, (ndocs + 3) / 4));
   const uint32_t ngroups = doc_groups(ndocs);
@@ -3301,7 +3306,7 @@ hipError_t run_batch(const BatchTables &bt, const uint8_t *bytes, uint64_t nbyte
   }
   mark(ev, 1, s);
   if (e == hipSuccess) {  // speculative walks, then the lanes of documents not split by them
-    k_bcount<1><<<(uint32_t)cus * per_cu_c, 256, lds_c, s>>>(a);
+    k_bcount<1><<<(uint32_t)cus * per_cu_c, 1024, lds_c, s>>>(a);
     e = hipGetLastError();
   }
   if (e == hipSuccess) {  // the hybrid plan's cuts
@@ -3309,7 +3314,7 @@ hipError_t run_batch(const BatchTables &bt, const uint8_t *bytes, uint64_t nbyte
     e = hipGetLastError();
   }
   if (e == hipSuccess) {  // the lanes of the split documents
-    k_bcount<2><<<(uint32_t)cus * per_cu_c, 256, lds_c, s>>>(a);
+    k_bcount<2><<<(uint32_t)cus * per_cu_c4, 256, lds_c, s>>>(a);
     e = hipGetLastError();
   }
   mark(ev, 2, s);
