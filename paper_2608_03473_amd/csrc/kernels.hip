@@ -1875,7 +1875,7 @@ struct DocResDev {  // mirrors lex_doc_result
 // meta words: work queues (count, lane emit, windowed emit), lane / speculative-lane / tile
 // totals, a stopped batch, no windowed emit for this batch, some document for the lane emit
 enum { kQCount = 0, kQEmit = 1, kNLanes = 2, kBad = 3, kNSpec = 4, kQWin = 5, kNTiles = 6, kNoWin = 7,
-       kAnyLane = 8, kQCount2 = 9, kBatchMeta = 16 };
+       kAnyLane = 8, kBatchMeta = 16 };
 
 struct BatchArgs {
   const uint32_t *table;
@@ -1895,6 +1895,7 @@ struct BatchArgs {
   // per speculative lane its document, cut, last restart, and head then tail token starts
   uint32_t spec_bytes, max_spec;
   uint32_t *spec_base, *spec_fail, *spec_doc, *spec_cut, *spec_rst, *spec_bits;
+  uint4 *spec_part, *spec_pre;  // per speculative lane: its parts' starts and count prefixes (k_bsplit)
   // windowed emit: count-walk checkpoints (main slots per lane, kslots of them, and an
   // overflow region of 64 windows per tile of each document), tiles of 64 windows per
   // document (prefix and tile -> document map), per lane the last non-empty lane at or
@@ -1966,8 +1967,10 @@ __device__ __forceinline__ uint32_t refused_mask(const BatchArgs &a) {
   return m;
 }
 
+// A refused set's document longer than a speculative lane and than the batch lane is split
+// by the hybrid plan; a shorter one is one lane among the certified documents' lanes.
 __device__ __forceinline__ bool spec_split(const BatchArgs &a, uint32_t rm, const DocDev &d) {
-  return d.inst < a.ninst && ((rm >> d.inst) & 1) && !(d.flags & 1) && d.length > a.spec_bytes;
+  return d.inst < a.ninst && ((rm >> d.inst) & 1) && !(d.flags & 1) && d.length > max(a.spec_bytes, a.lane_bytes);
 }
 
 __device__ __forceinline__ bool one_lane(const BatchArgs &a, uint32_t rm, const DocDev &d) {
@@ -2083,7 +2086,6 @@ __global__ void __launch_bounds__(256) k_bplan_a(BatchArgs a) {
   const uint32_t rm = refused_mask(a);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     a.meta[kQCount] = 0;
-    a.meta[kQCount2] = 0;
     a.meta[kQEmit] = 0;
     a.meta[kQWin] = 0;
     a.meta[kAnyLane] = 0;
@@ -2430,39 +2432,30 @@ __device__ __forceinline__ uint32_t next_tile(uint32_t *q) {
 }
 
 // Count walk of the batch: each lane places its own slice inside its document (the fused
-// planner) and counts it with its document's table.  Two passes around the hybrid plan's
-// cuts.  PASS 1 takes tiles from one queue: first the speculative lanes' walks (few and
-// serial, they would leave the chip idle in a launch of their own), then the lanes of every
-// document that is not split by the hybrid plan, which keep the chip busy meanwhile.
-// PASS 2, after the cuts, counts the split documents' lanes, taken through the
-// speculative lanes' numbering (a split document's lanes are its speculative lanes).
-template <int PASS>
+// planner) and counts it with its document's table.  One queue hands out, first, the
+// hybrid plan's speculative walks (few and serial, they would leave the chip idle in a
+// launch of their own), then the lanes of every document the hybrid plan does not split,
+// which keep the chip busy meanwhile.  The split documents are counted after the cuts
+// (k_bsplit).
 __global__ void __launch_bounds__(1024) k_bcount(BatchArgs a) {
   const BatchLds l = batch_stage(a);
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t nlanes = a.meta[kNLanes], nspec = a.meta[kNSpec];
-  const uint32_t nst = PASS == 1 ? (nspec + 63) / 64 : 0;  // speculative tiles first
+  const uint32_t nst = (nspec + 63) / 64;  // speculative tiles first
   const bool ck_on = !a.meta[kNoWin];
-  for (;;) {
-    const uint32_t tile = next_tile(&a.meta[PASS == 1 ? kQCount : kQCount2]);
-    if (PASS == 1 && tile < nst) {  // wave-uniform
+  // every wave's first tile is fixed (all waves taking it from the queue at once would
+  // queue on its atomic counter); later ones come from the queue, past the fixed ones
+  const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6, gw = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  for (uint32_t tile = gw;; tile = next_tile(&a.meta[kQCount]) + nwaves) {
+    if (tile < nst) {  // wave-uniform
       const uint32_t i = tile * 64 + lane;
       if (i < nspec) spec_lane(a, l, i);
       continue;
     }
     const uint32_t t = tile - nst;
-    if ((uint64_t)t * 64 >= (PASS == 1 ? nlanes : nspec)) break;  // wave-uniform exit
-    bool valid;
-    uint32_t j;
-    if (PASS == 1) {
-      j = t * 64 + lane;
-      valid = j < nlanes;
-    } else {
-      const uint32_t i = t * 64 + lane;
-      valid = i < nspec;
-      const uint32_t ds = valid ? a.spec_doc[i] : 0;
-      j = valid ? a.lane_base[ds] + (i - a.spec_base[ds]) : 0;
-    }
+    if ((uint64_t)t * 64 >= nlanes) break;  // wave-uniform exit
+    const uint32_t j = t * 64 + lane;
+    const bool valid = j < nlanes;
     uint32_t d = 0, jj = 0, nl = 1, start = kNone;
     DocDev doc{0, 0, 0, 0};
     if (valid) {
@@ -2481,19 +2474,10 @@ __global__ void __launch_bounds__(1024) k_bcount(BatchArgs a) {
     }
     // the next lane's start, when that lane is this document's and this tile's
     const uint32_t nstart = (uint32_t)__shfl_down((int)start, 1);
-    if (!valid || (PASS == 1 && spec)) continue;
+    if (!valid || spec) continue;
     const bool same = lane < 63 && jj + 1 < nl;
     uint32_t s, e;
-    if (spec) {  // the hybrid plan's slice, or the whole document on one lane
-      const uint32_t i = a.spec_base[d] + jj;
-      if (a.spec_fail[d]) {
-        s = jj ? doc.length : 0;
-        e = doc.length;
-      } else {
-        s = a.spec_cut[i];
-        e = jj + 1 < nl ? a.spec_cut[i + 1] : doc.length;
-      }
-    } else if (start == kNone) {
+    if (start == kNone) {
       s = e = min(jj * a.lane_bytes, doc.length);
     } else {
       s = start;
@@ -2520,7 +2504,7 @@ __global__ void __launch_bounds__(1024) k_bcount(BatchArgs a) {
       ck.nlanes = a.max_lanes;
       ck.kslots = a.kslots;
       ck.j = j;
-      ck.jl = jj * (spec ? a.spec_bytes : a.lane_bytes);
+      ck.jl = jj * a.lane_bytes;
       ck.mis0 = (uint32_t)(ck.base & (kWin - 1));
     }
     const bool halted = in.mono ? walk<false, true, false, true>(L, r, tb, src, doc.length, s, e, ck)
@@ -2529,6 +2513,125 @@ __global__ void __launch_bounds__(1024) k_bcount(BatchArgs a) {
     // bit 0: the slice halted; bit 1: no windowed emit for its document (a fallback
     // re-scanned positions the checkpoints describe, or counts overflow 24 bits)
     a.halted[j] = (halted ? 1u : 0u) | ((L.fb || e - s >= (1u << 24)) ? 2u : 0u);
+  }
+}
+
+// The first token start of speculative lane i's walk at or after x and before e (else e):
+// lane k = i's place in its document walked [k S, (k+1) S + kSpecX) and marked its token
+// starts in head ([k S, k S + kSpecX), kSpecX = S) and tail ([b2, b2 + kSpecX)).  Past the
+// lane's cut they are serial token starts (its walk is the serial scan from there on).
+__device__ __forceinline__ uint32_t spec_next_start(const BatchArgs &a, uint32_t i, uint32_t k, uint32_t len,
+                                                    uint32_t x, uint32_t e) {
+  const uint32_t *head = a.spec_bits + (size_t)i * 2 * kSpecWords, *tail = head + kSpecWords;
+  const uint32_t b = k * a.spec_bytes;
+  const uint32_t b2 = (uint32_t)min<uint64_t>((uint64_t)(k + 1) * a.spec_bytes, len);
+  // four bitmap words (128 positions) per load: the search is a chain of dependent loads
+  for (uint32_t pos = x; pos < e;) {
+    const bool h = pos < b2;
+    const uint32_t base = h ? b : b2, off = pos - base;
+    if (off >= kSpecX) break;  // past the bitmaps
+    const uint32_t w0 = (off >> 5) & ~3u;  // 16-byte aligned: the bitmaps start 256-byte aligned
+    const uint4 v = *reinterpret_cast<const uint4 *>((h ? head : tail) + w0);
+    const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (uint32_t u = 0; u < 4; ++u) {
+      const uint32_t at = 32 * (w0 + u);  // bitmap position of the word's bit 0
+      const uint32_t m = at + 32 <= off ? 0u : at >= off ? wv[u] : wv[u] & (~0u << (off - at));
+      if (m) return min(e, base + at + (uint32_t)(__ffs(m) - 1));
+    }
+    pos = base + 32 * (w0 + 4);
+  }
+  return e;
+}
+
+// Count walks of the documents the hybrid plan splits, after the cuts.  A split document's
+// lane is its speculative lane's slice [s, e).  kParts threads walk it, in parts cut at the
+// speculative walk's token starts (serial ones past the cut): part q starts at the first at
+// or after s + q (e - s) / kParts, so each walk is about a quarter of a slice (these walks are
+// few, and one walk's length sets the kernel's time).  A part's checkpoints count from the
+// part's own start, and the windowed emit adds the counts of the parts before it
+// (spec_part: the parts' starts, spec_pre: their inclusive count prefixes).  A document
+// that falls back to one lane is not split further: its walk may restart where the serial
+// scan halts, so its token starts are not all serial.
+constexpr uint32_t kParts = 4;
+__global__ void __launch_bounds__(256) k_bsplit(BatchArgs a) {
+  const BatchLds l = batch_stage(a);
+  const uint32_t lane = threadIdx.x & 63, q = lane % kParts, g0 = lane - q;
+  const uint32_t nspec = a.meta[kNSpec];
+  const bool ck_on = !a.meta[kNoWin];
+  constexpr uint32_t kPer = 64 / kParts;  // speculative lanes per 64-thread tile
+  // a tile per wave, in a fixed order: the walks are about one per wave, and a queue's
+  // atomic counter, which every wave would hit at once, costs more than the walks
+  const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6, gw = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  for (uint32_t t = gw; (uint64_t)t * kPer < nspec; t += nwaves) {  // wave-uniform
+    const uint32_t i = t * kPer + lane / kParts;
+    const bool valid = i < nspec;
+    uint32_t s = 0, e = 0, k = 0, j = 0, d = 0;
+    bool fail = true;
+    DocDev doc{0, 0, 0, 0};
+    if (valid) {
+      d = a.spec_doc[i];
+      doc = a.docs[d];
+      k = i - a.spec_base[d];
+      j = a.lane_base[d] + k;
+      fail = a.spec_fail[d] != 0;
+      if (fail) {
+        s = k ? doc.length : 0;
+        e = doc.length;
+      } else {
+        s = a.spec_cut[i];
+        e = k + 1 < a.lanes_of[d] ? a.spec_cut[i + 1] : doc.length;
+      }
+    }
+    uint32_t p = s;  // this part's start
+    if (q) p = valid && !fail ? spec_next_start(a, i, k, doc.length, s + (uint32_t)((uint64_t)(e - s) * q / kParts), e) : e;
+    const uint32_t pn = (uint32_t)__shfl_down((int)p, 1);
+    const uint32_t pe = q + 1 < kParts ? pn : e;  // this part's end
+    const BatchInst &in = a.inst[valid ? doc.inst : 0];
+    const uint8_t *src = a.bytes + doc.offset;
+    const Tables tb{l.T, l.info, l.kind, in.sink, in.fail, in.start};
+    LaneState L;
+    L.cnt = 0;
+    L.fb = 0;
+    Ring r{};
+    bool halted = false;
+    if (valid) {
+      CkSink ck{};
+      if (ck_on) {
+        ck.base = reinterpret_cast<uintptr_t>(src);
+        ck.main = a.ck_main;
+        ck.over = a.ck_over + (size_t)a.tile_base[d] * 64;
+        ck.nlanes = a.max_lanes;
+        ck.kslots = a.kslots;
+        ck.j = j;
+        ck.jl = k * a.spec_bytes;
+        ck.mis0 = (uint32_t)(ck.base & (kWin - 1));
+      }
+      halted = in.mono ? walk<false, true, false, true>(L, r, tb, src, doc.length, p, pe, ck)
+                       : walk<false, false, false, true>(L, r, tb, src, doc.length, p, pe, ck);
+    }
+    // the lane's count: its parts' up to the first that halted; inclusive prefixes in the group
+    uint32_t pre = valid ? L.cnt : 0;
+    for (uint32_t dd = 1; dd < kParts; dd <<= 1) {
+      const uint32_t v = (uint32_t)__shfl_up((int)pre, dd);
+      if (q >= dd) pre += v;
+    }
+    const unsigned long long hb = __ballot(valid && halted), fb = __ballot(valid && L.fb);
+    const uint32_t gh = (uint32_t)(hb >> g0) & ((1u << kParts) - 1), gf = (uint32_t)(fb >> g0) & ((1u << kParts) - 1);
+    const uint32_t qh = gh ? (uint32_t)__ffs(gh) - 1 : kParts - 1;
+    const uint32_t tot = (uint32_t)__shfl((int)pre, g0 + qh);
+    const uint32_t pre0 = (uint32_t)__shfl((int)pre, g0), pre1 = (uint32_t)__shfl((int)pre, g0 + 1),
+                   pre2 = (uint32_t)__shfl((int)pre, g0 + 2);
+    const uint32_t p1 = (uint32_t)__shfl((int)p, g0 + 1), p2 = (uint32_t)__shfl((int)p, g0 + 2),
+                   p3 = (uint32_t)__shfl((int)p, g0 + 3);
+    if (valid && q == 0) {
+      a.cuts[j] = s;
+      a.ends[j] = e;
+      a.counts[j] = tot;
+      a.halted[j] = (gh ? 1u : 0u) | ((gf || e - s >= (1u << 24)) ? 2u : 0u);
+      a.spec_part[i] = make_uint4(p1, p2, p3, 0);
+      a.spec_pre[i] = make_uint4(pre0, pre1, pre2, 0);
+    }
   }
 }
 
@@ -2739,6 +2842,7 @@ struct BDoc {
   uint32_t len, mis0, nwin, lb, nl, lnom, out0, lim;
   const uint2 *over;
   uint32_t inst;
+  uint32_t sb;  // split by the hybrid plan: its first speculative lane, else kNone
 };
 
 // First-round loads for window i of the document (the candidate owner's slice and the last
@@ -2774,11 +2878,27 @@ __device__ __forceinline__ WinMeta bwin_meta(const BatchArgs &a, const BDoc &c, 
     m.fresh = 1;
     return m;
   }
+  // A split document's slice was counted in parts (k_bsplit): the counts of the parts before
+  // this window's come on top of its checkpoint's, and a window starting a part starts a
+  // token, as at a lane start (the window before it then ends the token in progress).
+  uint32_t add = 0;
+  if (c.sb != kNone) {
+    const uint4 pp = a.spec_part[c.sb + (j - c.lb)], pr = a.spec_pre[c.sb + (j - c.lb)];
+    const uint32_t q = (r.ws >= pp.x) + (r.ws >= pp.y) + (r.ws >= pp.z);
+    add = q == 3 ? pr.z : q == 2 ? pr.y : q == 1 ? pr.x : 0;
+    if (r.ws == pp.x || r.ws == pp.y || r.ws == pp.z) {
+      m.st = in.start;
+      m.tok = r.ws;
+      m.out = base + add;
+      m.fresh = 1;
+      return m;
+    }
+  }
   const uint32_t k = (r.ws - (j - c.lb) * c.lnom) / kWin;
   const uint2 ck = k < a.kslots ? a.ck_main[ck_index(k, j, a.max_lanes)] : c.over[i];
   m.st = row_state(ck.x >> 24);
   m.tok = ck.y;
-  m.out = base + (ck.x & 0xFFFFFFu);
+  m.out = base + (ck.x & 0xFFFFFFu) + add;
   return m;
 }
 
@@ -2811,7 +2931,9 @@ __global__ void __launch_bounds__(1024) k_bemit_win(BatchArgs a) {
     if (!a.doc_win[d]) continue;
     c.lb = a.lane_base[d];
     c.nl = a.lanes_of[d];
-    c.lnom = spec_split(a, rm, doc) ? a.spec_bytes : a.lane_bytes;
+    const bool split = spec_split(a, rm, doc);
+    c.lnom = split ? a.spec_bytes : a.lane_bytes;
+    c.sb = split ? a.spec_base[d] : kNone;
     c.out0 = (uint32_t)a.res[d].tok_offset;
     c.lim = c.out0 + (uint32_t)a.res[d].ntokens;  // the document's outputs end here
     c.over = a.ck_over + (size_t)tb0 * 64;
@@ -3199,7 +3321,8 @@ size_t batch_workspace_bytes(uint32_t ndocs, uint64_t nbytes, uint32_t lane_byte
   const uint64_t nt = batch_max_tiles(ndocs, nbytes);
   const size_t per_doc = align256((size_t)std::max<uint32_t>(ndocs, 1) * 4);
   return align256(kBatchMeta * 4) + align256((size_t)kDocGroups * kPartWords * 8) + 9 * per_doc + 7 * align256((size_t)nl * 4) + 3 * align256((size_t)ns * 4) +
-         align256((size_t)ns * 2 * kSpecWords * 4) + align256((size_t)ck_slots(lane_bytes) * nl * 8) +
+         align256((size_t)ns * 2 * kSpecWords * 4) + 2 * align256((size_t)ns * 16) +
+         align256((size_t)ck_slots(lane_bytes) * nl * 8) +
          align256((size_t)nt * 64 * 8) + align256((size_t)nt * 4);
 }
 
@@ -3259,6 +3382,8 @@ hipError_t run_batch(const BatchTables &bt, const uint8_t *bytes, uint64_t nbyte
   a.spec_cut = reinterpret_cast<uint32_t *>(w), w += per_spec;
   a.spec_rst = reinterpret_cast<uint32_t *>(w), w += per_spec;
   a.spec_bits = reinterpret_cast<uint32_t *>(w), w += align256((size_t)a.max_spec * 2 * kSpecWords * 4);
+  a.spec_part = reinterpret_cast<uint4 *>(w), w += align256((size_t)a.max_spec * 16);
+  a.spec_pre = reinterpret_cast<uint4 *>(w), w += align256((size_t)a.max_spec * 16);
   const size_t per_lane = align256((size_t)batch_max_lanes(ndocs, nbytes, lane_bytes) * 4);
   a.lane_doc = reinterpret_cast<uint32_t *>(w), w += per_lane;
   a.cuts = reinterpret_cast<uint32_t *>(w), w += per_lane;
@@ -3284,12 +3409,19 @@ hipError_t run_batch(const BatchTables &bt, const uint8_t *bytes, uint64_t nbyte
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   const size_t lds_c = batch_lds_offset(bt.nrows, bt.ninst);
-  // the first count pass: workgroups of 16 waves, so that one copy of the combined table in
-  // LDS serves the four waves per SIMD the kernel's registers allow (workgroups of 4 waves,
-  // each with its own copy, ran out of LDS at three per CU when the table is large); the
-  // second, a few serial walks, spreads them over more CUs in workgroups of 4 waves
-  const uint32_t per_cu_c = (uint32_t)std::max<size_t>(1, std::min<size_t>(2, 160 * 1024 / lds_c));
-  const uint32_t per_cu_c4 = (uint32_t)std::min<size_t>(8, 160 * 1024 / lds_c);
+  // The count walk: workgroups of 16 waves, so that one copy of the combined table in LDS
+  // serves the waves per SIMD the kernel's registers allow (workgroups of 4 waves, each with
+  // its own copy, ran out of LDS at three per CU when the table is large).  The split
+  // documents' walks, a few serial ones, spread over more CUs in workgroups of 4 waves.
+  // Both grids are what the CUs hold at once: each wave's first tile is fixed, and a
+  // workgroup that waited for a free CU would take its fixed tiles last.
+  auto resident = [&](const void *k, int threads) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, threads, lds_c) != hipSuccess || nb < 1) nb = 1;
+    return (uint32_t)nb;
+  };
+  const uint32_t per_cu_c = resident(reinterpret_cast<const void *>(k_bcount), 1024);
+  const uint32_t per_cu_c4 = resident(reinterpret_cast<const void *>(k_bsplit), 256);
   const uint32_t per_cu_e = (uint32_t)std::min<size_t>(8, 160 * 1024 / lds_e);
   const uint32_t gdoc = std::max<uint32_t>(1, std::min<uint32_t>(4096, (ndocs + 3) / 4));
   const uint32_t ngroups = doc_groups(ndocs);
@@ -3306,7 +3438,7 @@ hipError_t run_batch(const BatchTables &bt, const uint8_t *bytes, uint64_t nbyte
   }
   mark(ev, 1, s);
   if (e == hipSuccess) {  // speculative walks, then the lanes of documents not split by them
-    k_bcount<1><<<(uint32_t)cus * per_cu_c, 1024, lds_c, s>>>(a);
+    k_bcount<<<(uint32_t)cus * per_cu_c, 1024, lds_c, s>>>(a);
     e = hipGetLastError();
   }
   if (e == hipSuccess) {  // the hybrid plan's cuts
@@ -3314,7 +3446,7 @@ hipError_t run_batch(const BatchTables &bt, const uint8_t *bytes, uint64_t nbyte
     e = hipGetLastError();
   }
   if (e == hipSuccess) {  // the lanes of the split documents
-    k_bcount<2><<<(uint32_t)cus * per_cu_c4, 256, lds_c, s>>>(a);
+    k_bsplit<<<(uint32_t)cus * per_cu_c4, 256, lds_c, s>>>(a);
     e = hipGetLastError();
   }
   mark(ev, 2, s);

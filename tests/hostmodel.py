@@ -336,3 +336,23 @@ def spec_plan(model, w: bytes, S: int, X: int):
         if rst is not None and rst >= cuts[k]:
             return None
     return cuts
+
+
+def spec_parts(model, w: bytes, S: int, cuts, parts: int = 4):
+    """The batch's split of each hybrid-plan slice [s, e) into `parts` walks (S = the sync
+    window = the speculative lane): part q > 0 starts at the first token start of lane k's
+    speculative walk at or after s + q (e - s) // parts and before e, looked up only where
+    the walk marked them (head [k S, (k+1) S), tail [(k+1) S, (k+2) S)), else at e.  Returns
+    per slice the list of part starts (parts entries, the first being s)."""
+    n = len(w)
+    out = []
+    for k, (s, e) in enumerate(zip(cuts, cuts[1:] + [n])):
+        starts, _ = spec_walk(model, w, k * S, min((k + 1) * S + S, n))
+        b2 = min((k + 1) * S, n)
+        marked = sorted(t for t in starts if (k * S <= t < k * S + S) or (b2 <= t < b2 + S))
+        ps = [s]
+        for q in range(1, parts):
+            x = s + (e - s) * q // parts
+            ps.append(next((t for t in marked if x <= t < e), e))
+        out.append(ps)
+    return out

@@ -134,6 +134,27 @@ def test_hybrid_plan_model():
             got += list(zip(k.tolist(), l.tolist(), (o + a).tolist()))
         assert got == list(zip(kd.tolist(), ld.tolist(), od.tolist())), seed
     assert split >= 8
+    # the batch's parameters (S = X = 2 KiB) and its four-part walks of each slice: every part
+    # start is a serial token start, and the parts lexed alone concatenate to the serial scan
+    parted = 0
+    for seed in range(6):
+        w = bytes(workloads.clike([20000, 50000][seed % 2], 900 + seed, bcomment=True))
+        cuts = hostmodel.spec_plan(m, w, 2048, 2048)
+        if cuts is None:
+            continue
+        kd, ld, od, _ = oc.lex(w, discard=True, offsets=True)
+        serial_starts = set(oc.lex(w, discard=False, offsets=True)[2].tolist())
+        got = []
+        for ps, (s0, e0) in zip(hostmodel.spec_parts(m, w, 2048, cuts), zip(cuts, cuts[1:] + [len(w)])):
+            assert ps == sorted(ps) and all(s0 <= p <= e0 for p in ps)
+            assert all(p in serial_starts or p == e0 for p in ps[1:]), seed
+            parted += sum(1 for p in ps[1:] if s0 < p < e0)
+            for a, b in zip(ps, ps[1:] + [e0]):
+                k, l, o, c = oc.lex(w[a:b], discard=True, offsets=True)
+                assert c == b - a
+                got += list(zip(k.tolist(), l.tolist(), (o + a).tolist()))
+        assert got == list(zip(kd.tolist(), ld.tolist(), od.tolist())), seed
+    assert parted > 20
     # malformed: the serial scan halts, so the plan falls back
     w = bytearray(workloads.clike(30000, 9, bcomment=True))
     w[12000:12002] = b"@@"
