@@ -20,9 +20,10 @@
 //   (e) k_emit       every lane up to the first halted one walks again and writes its
 //                    (kind, length[, offset]) triples at its prefix offset, skipping
 //                    discarded kinds in modulo-I mode (the image pi_I of Section 5).
-//                    Tokens are staged in a 64-byte per-lane LDS ring and leave in whole,
-//                    aligned 32-byte sectors (8 lengths or 32 kinds at a time), so the
-//                    emit walk issues few, full-width memory requests.
+//                    Tokens are staged in a 96-byte per-lane LDS ring (16 packed length
+//                    words, 32 kinds) and leave in whole, aligned 32-byte sectors (8
+//                    lengths or 32 kinds at a time), so the emit walk issues few,
+//                    full-width memory requests.
 //       k_emit_win   the windowed emit: one thread per 64-byte window, restarted from
 //                    the count walk's checkpoint, tokens staged per wave (their ends, or
 //                    their lengths in a mode with discarded kinds) and written out
@@ -1828,14 +1829,15 @@ __global__ void k_onepass_reset(uint64_t *st, uint32_t n, uint32_t *ctr) {
 // them sit in LDS.  Each document is split into lanes exactly as a single scan would split
 // it (Theorem 1, Theorem 3): lane jj of a document targets jj * lane_bytes inside it, and a
 // document whose useful map is empty, or that asks for a serial scan, is one lane.  Lanes
-// are numbered long single-lane documents first, so the longest walks start first; count
-// and emit workgroups pull 64-lane tiles from atomic queues (work stealing).  Each
-// document's result is its own scan's: its tokens up to and including its first halted
-// slice, error offset relative to the document.
+// are numbered long single-lane documents first, so the longest walks start first; the
+// count workgroups take 64-lane tiles from an atomic queue (work stealing) after a first
+// tile fixed per wave, and the windowed emit gives each wave a contiguous range of tiles.
+// Each document's result is its own scan's: its tokens up to and including its first
+// halted slice, error offset relative to the document.
 //
 // Hybrid plan for refused token sets: a document of such a set (no useful certified byte),
-// not flagged serial and longer than one speculative lane (kSpecX bytes) is split
-// speculatively.  Lane k starts at k * S in the start row as if a token
+// not flagged serial and longer than one speculative lane (kSpecX bytes) and than the batch
+// lane is split speculatively.  Lane k starts at k * S in the start row as if a token
 // began there, walks its range and kSpecX bytes on, and restarts one byte further on after
 // a halt, recording the token starts of its first kSpecX bytes (head) and of the kSpecX
 // bytes after its range (tail).  Lane 0 is the serial scan.  If lane k - 1's walk is the
@@ -1872,8 +1874,9 @@ struct DocResDev {  // mirrors lex_doc_result
   uint32_t nslices;
 };
 
-// meta words: work queues (count, lane emit, windowed emit), lane / speculative-lane / tile
-// totals, a stopped batch, no windowed emit for this batch, some document for the lane emit
+// meta words: work queues (count, lane emit; kQWin is reset but no kernel takes from it),
+// lane / speculative-lane / tile totals, a stopped batch, no windowed emit for this batch,
+// some document for the lane emit
 enum { kQCount = 0, kQEmit = 1, kNLanes = 2, kBad = 3, kNSpec = 4, kQWin = 5, kNTiles = 6, kNoWin = 7,
        kAnyLane = 8, kBatchMeta = 16 };
 
@@ -2829,7 +2832,7 @@ __global__ void __launch_bounds__(256) k_bemit(BatchArgs a) {
 
 // The windowed emit over a batch's documents.  Work items are tiles of 64 windows of one
 // document (windows: the kWin-aligned stretches of the address space, clipped to the
-// document), taken from a queue; each wave walks one tile at a time, a window per thread,
+// document), in contiguous ranges per wave; each wave walks one tile at a time, a window per thread,
 // from the count walk's checkpoint, stages the tile's tokens and writes them out coalesced,
 // exactly as the single-buffer windowed emit does with the document as its input (its
 // slices, cut at certified bytes or at the hybrid plan's serial token starts, are the
