@@ -204,3 +204,50 @@ def test_batch_refused_hybrid_plan(setup):
     # the last lane empty: the previous one takes the rest (lanes of SPEC_LANE bytes)
     assert ns[9] == -(-8400 // SPEC_LANE) - 1, ns
     assert ns[5] >= 3000000 // 4096 // 2
+
+
+@pytest.mark.parametrize("lane", [1024, 2048, 4096, 8192])
+def test_batch_split_parts_at_batch_lanes(setup, lane):
+    """The hybrid plan at the batch lanes the bench and the tuner use: a refused document
+    longer than both the speculative lane (2 KiB) and the batch lane is split, and each slice
+    is counted in four parts cut at serial token starts; the windowed emit adds the earlier
+    parts' counts and starts a token at a window that begins a part.  Documents of many
+    lengths (around 2, 4 and 8 KiB, and long ones), dense code and long (but shorter than the
+    sync window) block comments near lane boundaries, with and without offsets: every
+    document equals the oracle's serial scan, and those the plan splits report several
+    slices."""
+    cb = INSTANCES.index(("clike_b", 1))
+    parts, recs, off = [], [], 0
+    rng = np.random.default_rng(lane)
+    lengths = [2047, 2048, 2049, 2100, 4095, 4096, 4097, 5000, 8191, 8193, 12000, 65536, 250000]
+    for i, n in enumerate(lengths):
+        b = np.array(workloads.clike(n, 2000 + i, bcomment=True), copy=True)
+        parts.append(b)
+        recs.append((off, n, cb, 0))
+        off += n
+    for i in range(6):  # comments of 300-1500 bytes starting just before 2 KiB boundaries
+        b = bytearray()
+        for k in range(1, 6):
+            start = k * 2048 - int(rng.integers(50, 600))
+            if len(b) < start:
+                b += bytes(workloads.clike(start - len(b), 2100 + 10 * i + k))
+            b += b"\n/* " + b"c" * int(rng.integers(300, 1500)) + b" */\n"
+        b += bytes(workloads.clike(3000, 2190 + i))
+        parts.append(np.frombuffer(bytes(b), np.uint8))
+        recs.append((off, len(b), cb, 0))
+        off += len(b)
+    data = np.concatenate(parts)
+    docs = np.array(recs, dtype=P.DOC_DTYPE)
+    print(f"[case] split parts, batch lane {lane}: {docs.size} C-like-B documents, {data.size} B", flush=True)
+    _, _, batch = setup
+    opts = P.RunOpts(lane_bytes=lane)
+    for offsets in (True, False):
+        r = batch.run(torch.from_numpy(data).cuda(), docs, offsets=offsets, opts=opts)
+        check_batch(setup, data, docs, r)
+    ns = r.docs["nslices"]
+    thr = max(2048, lane)
+    for i, n in enumerate(lengths):
+        if n > thr + 4096:
+            assert ns[i] > 1, (i, n, ns[i])
+        if n <= thr:
+            assert ns[i] <= 1, (i, n, ns[i])  # one lane
