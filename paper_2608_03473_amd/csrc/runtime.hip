@@ -567,13 +567,13 @@ void lex_batch_free(lex_batch *b) {
   delete b;
 }
 
-// Default batch lane: 1 KiB, doubled while the batch would have more than about 1M lanes,
+// Default batch lane: 1 KiB, doubled while the batch would have more than about 2M lanes,
 // up to 4 KiB.  Below that count a lane's fixed costs (plan entry, count, scan slot, emit
-// start) are small beside its walk; above it they dominate, and longer lanes pay (lanes
-// longer than the speculative lane also lengthen the hybrid plan's walks).
+// start) are small beside its walk; above it they dominate, and longer lanes pay.  (On the
+// 50 000-document, 2.5 GB batch, 2 KiB lanes measured 3.15 ms against 3.24 ms at 4 KiB.)
 static uint32_t batch_default_lane_bytes(uint64_t nbytes) {
   uint32_t l = 1024;
-  while (l < 4096 && nbytes / l > (1u << 20)) l <<= 1;
+  while (l < 4096 && nbytes / l > (2u << 20)) l <<= 1;
   return l;
 }
 
