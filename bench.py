@@ -150,7 +150,7 @@ def main():
     if status != 0 or err != n:
         print(f"bench: scan failed status={status} error_offset={err} n={n}", file=sys.stderr)
         sys.exit(1)
-    parity = stream_parity("clike_512mib", n, args.seed, args.chunk_bytes, ntok, err, kinds, lens)
+    parity = stream_parity("clike_512mib", n, args.seed, ntok, err, kinds, lens)
     phases = np.array([e.elapsed_ms() for e in evs])  # steps x 4
     ph_mean = phases.mean(axis=0)
     plan = lx.plan(n, mode, opts)
@@ -235,12 +235,12 @@ def _digests(kinds_np, lens_np):
     return SM.sha(kinds_np), SM.sha(lens_np.astype("<u4", copy=False))
 
 
-def stream_parity(name, n, seed, chunk_bytes, ntok, err, kinds, lens):
+def stream_parity(name, n, seed, ntok, err, kinds, lens):
     """Whole-stream parity of the last timed scan against the oracle's digests: token count,
     error offset, and the SHA-256 of every kind and every length.  None when the run is not
     the recorded workload."""
     case = manifest_case(name)
-    if case is None or case.get("n") != n or case.get("seed") != seed or chunk_bytes <= 0:
+    if case is None or case.get("n") != n or case.get("seed") != seed:
         return None
     if ntok != case["ntokens"] or err != case["error_offset"]:
         return False
@@ -578,9 +578,12 @@ def framed_leg(args):
         ms = (time.perf_counter() - t) * 1e3 / args.steps
         r = res.cpu().numpy()
         plan = lx.plan(n, mode)
+        par = stream_parity("clikeb_512mib_framed" if frame else "clikeb_512mib", n, args.seed, int(r[0]),
+                            int(r[1]), kinds, lens)
         out[key] = {"gbs": round(n / (ms * 1e-3) / 1e9, 3), "ms": round(ms, 3), "tokens": int(r[0]),
                     "error_offset": int(r[1]), "slices": int((int(r[2]) >> 32) & 0xFFFFFFFF),
-                    "path": plan["path"], "hybrid": plan["hybrid"], "lane_bytes": plan["lane_bytes"]}
+                    "path": plan["path"], "hybrid": plan["hybrid"], "lane_bytes": plan["lane_bytes"],
+                    "parity": par}
         if frame:
             out[key]["separators"] = int((host == 0x1E).sum())
         log(args, f"framed leg {key}: {out[key]}")

@@ -1,6 +1,7 @@
 """Whole-stream expected values for the benchmark workloads, written by the oracle.
 
-``python tests/golden/stream_manifest.py`` regenerates ``stream_manifest.json``.  It calls
+``python tests/golden/stream_manifest.py [case ...]`` regenerates ``stream_manifest.json``
+(every case, or only the named ones).  It calls
 only ``oracle/`` (the serial longest-match scan of Section 3, per-kind NFAs) and
 ``workloads/`` (the seeded corpus generators), never the HIP library.  For every case it
 records:
@@ -17,8 +18,10 @@ records:
 The cases are the benchmark configurations: the 1 MiB and 512 MiB C-like corpora in exact
 mode (seeds 1 and 2), both stray-byte variants of the 512 MiB corpus (seed 3: a draw whose
 line stops lexing, and one where 0x01 lands inside a string or comment and is legal), the
-256 MiB JSON corpus in modulo-I mode with offsets (seed 4) and every document of the
-50,000-document batch (seed 5).  The helpers below are shared with the GPU tests, which
+256 MiB JSON corpus in modulo-I mode with offsets (seed 4), every document of the
+50,000-document batch (seed 5), and the 512 MiB C-like corpus with block comments (seed 2)
+in exact mode under the C-like-B set: framed (records of 8 lines opened by 0x1E, the set
+framed by that byte, Section 7.1) and unframed (no certified byte: the hybrid plan).  The helpers below are shared with the GPU tests, which
 digest the device's output the same way.
 """
 from __future__ import annotations
@@ -48,6 +51,9 @@ CASES = {
     "clike_512mib_stray_ok": dict(gen="clike", n=512 << 20, seed=2, set="clike_l", mode=EXACT,
                                   stray_seed=3, want_error=False),
     "json_256mib": dict(gen="json", n=256 << 20, seed=4, set="json", mode=DISCARD, with_offsets=True),
+    "clikeb_512mib_framed": dict(gen="clike", n=512 << 20, seed=2, bcomment=True, frame=8, set="clike_b",
+                                 reserved=0x1E, mode=EXACT),
+    "clikeb_512mib": dict(gen="clike", n=512 << 20, seed=2, bcomment=True, frame=0, set="clike_b", mode=EXACT),
     "docs_50k": dict(gen="docs", count=50000, seed=5, sets=["clike_l", "clike_d", "clike_b"],
                      modes=[EXACT, DISCARD, DISCARD]),
 }
@@ -124,7 +130,8 @@ def corpus(case: dict, stray_offset: int | None = None):
     """The case's input bytes (for "docs": (bytes, offsets, sizes, set ids))."""
     import workloads
     if case["gen"] == "clike":
-        buf = workloads.clike(case["n"], case["seed"])
+        buf = workloads.clike(case["n"], case["seed"], bcomment=case.get("bcomment", False),
+                              frame=case.get("frame", 0))
         if stray_offset is not None:
             buf[stray_offset] = 1
         return buf
@@ -141,10 +148,11 @@ def load() -> dict:
 
 
 # ---------------------------------------------------------------------------- writer
-def _oracle_set(name):
+def _oracle_set(name, reserved=None):
+    """The oracle's compilation of a named set; reserved: framed by that byte (Section 7.1)."""
     import oracle
     from workloads import tokensets as T
-    return oracle.OracleSet(T.as_tuples(T.NAMED[name]))
+    return oracle.OracleSet(T.as_tuples(T.NAMED[name]), reserved=reserved)
 
 
 def pick_stray(buf, oc, seed, want_error):
@@ -167,7 +175,7 @@ def pick_stray(buf, oc, seed, want_error):
 def _single(name):
     case = CASES[name]
     t0 = time.time()
-    oc = _oracle_set(case["set"])
+    oc = _oracle_set(case["set"], case.get("reserved"))
     buf = corpus(case)
     out = {"corpus_sha256": sha(buf)}
     if "stray_seed" in case:
@@ -223,18 +231,24 @@ def _docs(pool, workers):
     return "docs_50k", head
 
 
-def main():
+def main(names=None):
+    """Write every case, or only `names`, keeping the other cases' recorded values."""
     from concurrent.futures import ProcessPoolExecutor
     sys.path.insert(0, ROOT)
     workers = min(8, os.cpu_count() or 1)
+    names = list(CASES) if not names else names
+    assert all(n in CASES for n in names), names
+    keep = load()["cases"] if os.path.exists(PATH) and len(names) < len(CASES) else {}
     out = {"about": ("Written by tests/golden/stream_manifest.py from the oracle (serial longest-match "
                      "scan, Section 3; Corollary 1 on malformed input) over the seeded corpora of "
                      "workloads/; never from the HIP library."),
            "block_tokens": BLOCK_TOKENS, "doc_block": DOC_BLOCK, "cases": {}}
+    out["cases"].update({k: v for k, v in keep.items() if k in CASES and k not in names})
     with ProcessPoolExecutor(workers) as pool:
-        singles = [pool.submit(_single, name) for name in CASES if name != "docs_50k"]
-        name, d = _docs(pool, workers)
-        out["cases"][name] = dict(CASES[name], **d)
+        singles = [pool.submit(_single, name) for name in names if name != "docs_50k"]
+        if "docs_50k" in names:
+            name, d = _docs(pool, workers)
+            out["cases"][name] = dict(CASES[name], **d)
         for f in singles:
             name, d = f.result()
             out["cases"][name] = dict(CASES[name], **d)
@@ -249,4 +263,4 @@ def main():
 
 if __name__ == "__main__":
     sys.path.insert(0, ROOT)
-    main()
+    main(sys.argv[1:])

@@ -1,15 +1,23 @@
 """GPU parity of framed scans (Section 7.1): a C-like-B set framed by the reserved byte 0x1E,
 compiled by lex_compile_framed, scanned through the C ABI single-buffer and batched, against
-the oracle's framed set, element by element.  The framed set certifies 0x1E, so a framed
-document takes the certified planner (several slices, no hybrid plan), where the unframed
-set is refused.  The bar is bit-exact kinds, lengths, offsets, token count and error offset.
+the oracle's framed set, element by element; at the benchmark's 512 MiB size, framed and
+unframed, every token against the whole-stream digests the oracle wrote.  The framed set
+certifies 0x1E, so a framed document takes the certified planner (several slices, no hybrid
+plan), where the unframed set is refused.  The bar is bit-exact kinds, lengths, offsets,
+token count and error offset.
 """
+import os
+import sys
+
 import numpy as np
 import pytest
 
 import oracle
 import workloads
 from workloads import tokensets as T
+
+sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+import stream_manifest as SM  # noqa: E402
 
 torch = pytest.importorskip("torch")
 P = pytest.importorskip("paper_2608_03473_amd")
@@ -189,3 +197,53 @@ def test_framed_full_size_sampled(sets):
         i0, i1 = np.searchsorted(offs, [a, b])
         np.testing.assert_array_equal(kinds[i0:i1], k)
         np.testing.assert_array_equal(lens[i0:i1], l)
+
+
+@pytest.mark.parametrize("name", ["clikeb_512mib_framed", "clikeb_512mib"])
+def test_clikeb_512mib_whole(sets, name):
+    """Every token of the benchmark's 512 MiB C-like-B scans, framed (the certified planner)
+    and unframed (no certified byte: the hybrid plan), in the launch configuration the
+    benchmark times (default plan, no offsets), against the oracle's whole-stream digests.
+    On a difference the first block of 2^20 tokens that differs is named and, framed,
+    re-lexed by the oracle from the separator before it to the one after it (0x1E is
+    certified under the framed set, so a scan may start there, Theorem 1)."""
+    want = SM.load()["cases"][name]
+    framed = "reserved" in want
+    n, mode = want["n"], P.LEX_MODE_EXACT
+    host = SM.corpus(want)
+    assert SM.sha(host) == want["corpus_sha256"], "C-like-B corpus generator drifted"
+    lx = sets["lx"] if framed else P.Lexer.compile(DEFS)
+    plan = lx.plan(n, mode)
+    assert bool(plan["hybrid"]) != framed
+    print(f"[case] {name} n={n} path={plan['path']} lane={plan['lane_bytes']} hybrid={plan['hybrid']}",
+          flush=True)
+    r = lx.run(torch.from_numpy(host).cuda(), mode=mode)
+    assert r.status == 0 and r.error_offset == want["error_offset"] == n
+    kinds = r.kinds.cpu().numpy()
+    lens = r.lens.cpu().numpy().view(np.uint32)
+    got = SM.stream_digest(kinds, lens)
+    if r.ntokens == want["ntokens"] and (got["kinds"], got["lens"]) == (want["kinds"], want["lens"]):
+        return
+    b = max(0, SM.first_bad_block(want["blocks"], got["blocks"]))
+    msg = (f"{name}: digests differ from the oracle's (first differing block {b}, "
+           f"{r.ntokens} tokens against {want['ntokens']})")
+    if framed and kinds.size:
+        starts = np.zeros(lens.size, np.int64)
+        np.cumsum(lens[:-1], out=starts[1:])
+        t0 = min(b * SM.BLOCK_TOKENS, kinds.size - 1)
+        t1 = min(kinds.size - 1, t0 + SM.BLOCK_TOKENS)
+        seps = np.flatnonzero(host == RS)
+        i = np.searchsorted(seps, starts[t0], side="right")
+        a = int(seps[i - 1]) if i else 0
+        j = np.searchsorted(seps, starts[t1], side="right")
+        e = int(seps[j]) if j < seps.size else n
+        k, l, o, con = sets["oc"].lex(bytes(host[a:e]), offsets=True)
+        lo, hi = np.searchsorted(starts, [a, a + con])
+        gk, gl, gs = kinds[lo:hi], lens[lo:hi], starts[lo:hi] - a
+        m = min(gk.size, k.size)
+        bad = np.flatnonzero((gk[:m] != k[:m]) | (gl[:m] != l[:m]) | (gs[:m] != o[:m].astype(np.int64)))
+        if bad.size:
+            x = int(bad[0])
+            msg += (f"; first differing token {lo + x} at byte {a + int(o[x])}: GPU (kind {gk[x]}, "
+                    f"len {gl[x]}) against oracle (kind {k[x]}, len {l[x]})")
+    raise AssertionError(msg)

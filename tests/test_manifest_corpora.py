@@ -30,9 +30,13 @@ def test_manifest_covers_the_benchmark_configurations():
     assert MAN["clike_512mib_stray_error"]["error_offset"] < 512 << 20
     assert MAN["clike_512mib_stray_ok"]["ntokens"] == MAN["clike_512mib"]["ntokens"]
     assert MAN["docs_50k"]["incomplete_documents"] == 0
+    for name in ("clikeb_512mib_framed", "clikeb_512mib"):
+        assert MAN[name]["error_offset"] == 512 << 20
+    # the framed corpus differs from the unframed one by its separators, each a token
+    assert MAN["clikeb_512mib_framed"]["ntokens"] > MAN["clikeb_512mib"]["ntokens"]
 
 
-@pytest.mark.parametrize("name", ["clike_1mib", "json_256mib"])
+@pytest.mark.parametrize("name", ["clike_1mib", "json_256mib", "clikeb_512mib_framed", "clikeb_512mib"])
 def test_corpus_digest(name):
     assert SM.sha(SM.corpus(MAN[name])) == MAN[name]["corpus_sha256"]
 
