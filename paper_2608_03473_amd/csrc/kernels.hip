@@ -1278,11 +1278,17 @@ __global__ void __launch_bounds__(1024) k_emit(WalkArgs a) {
 // start / lane_bytes when that lane is not empty and starts at or before it, otherwise
 // the last non-empty lane before j0 (slices tile the input, and a non-empty lane j starts
 // inside [j l, (j + 1) l)).
-constexpr int kWinWaves = 4;             // waves per workgroup
+constexpr int kWinWaves = 4;             // waves per workgroup of the one-pass kernel
 constexpr uint32_t kStageWords = 1280;   // staged words per wave
 
-__host__ __device__ inline size_t win_lds_bytes(int nrows) {
-  return lds_ring_offset(nrows) + (size_t)kWinWaves * kStageWords * 4;
+__host__ __device__ inline size_t win_lds_bytes(int nrows, uint32_t waves = kWinWaves) {
+  return lds_ring_offset(nrows) + (size_t)waves * kStageWords * 4;
+}
+// Waves of a windowed-emit workgroup: 16, 8 or 4, the most whose LDS fits in a CU.
+__host__ __device__ inline uint32_t win_waves(int nrows) {
+  for (uint32_t w = 16; w > 4; w >>= 1)
+    if (win_lds_bytes(nrows, w) <= 160 * 1024) return w;
+  return 4;
 }
 
 __device__ __forceinline__ void wave_sync() {
@@ -1515,13 +1521,22 @@ __device__ __forceinline__ void win_tile(const Tables &tb, const WalkArgs &a, ui
   wave_sync();
 }
 
-// A tile is 64 windows; each wave walks a contiguous run of tiles.  Software pipeline:
-// the next tile's bytes and the state of the tile after it load while a tile walks.
+// A tile is 64 windows.  A workgroup takes a contiguous range of tiles, and its waves
+// draw single tiles from it in order through a counter in LDS until the range runs dry:
+// the waves that the CU's arbitration lets run ahead take more tiles, so that they finish
+// together instead of the oldest first (with fixed runs per wave the youngest waves of a
+// CU finished 15% after its mean).  Software pipeline: the next tile's bytes and the
+// state of the tile after it load while a tile walks.  A tile's last window ends where
+// the first window of the tile after it (in the input) begins; that window's start is
+// read for every tile, uniformly across the wave, since a wave's next tile is seldom the
+// adjacent one.
 template <bool FUSED, bool DISC>
-__global__ void __launch_bounds__(256) k_emit_win(WalkArgs a) {
+__global__ void __launch_bounds__(1024) k_emit_win(WalkArgs a) {
   if (a.meta[0] != kNone || a.meta[1] != 0 || a.res->status != 0 || a.n == 0) return;
   const Lds l = carve_lds(a.nrows);
-  stage_tables(a, l, false);
+  uint32_t *ctr = l.red32;  // the workgroup's tile counter
+  if (threadIdx.x == 0) *ctr = 0;
+  stage_tables(a, l, false);  // its barrier publishes the zeroed counter
   const Tables tb{lds_bytes_of(l.T), l.info, l.kind, a.sink, a.fail, 0};
   const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   uint32_t *stage = reinterpret_cast<uint32_t *>(l.ring) + wid * kStageWords;
@@ -1530,38 +1545,60 @@ __global__ void __launch_bounds__(256) k_emit_win(WalkArgs a) {
   const uint32_t nwin = (uint32_t)(((uint64_t)a.n + mis0 + kWin - 1) / kWin);
   const uint32_t ntiles = (nwin + 63) / 64;
   const uint32_t ntok = (uint32_t)a.res->ntokens;  // every store below stays under it
-  const uint32_t nwaves = gridDim.x * kWinWaves, gw = blockIdx.x * kWinWaves + wid;
-  const uint32_t per = (ntiles + nwaves - 1) / nwaves;
-  const uint32_t t_lo = min(ntiles, gw * per), t_hi = min(ntiles, t_lo + per);
-  if (t_lo >= t_hi) return;  // wave-uniform, and no workgroup barrier follows
-  WinMeta cur = win_meta(a, win_r1<FUSED>(a, t_lo * 64 + lane, mis0, nwin), t_lo * 64 + lane, nwin, ntok);
-  WinMeta nxt = win_meta(a, win_r1<FUSED>(a, (t_lo + 1) * 64 + lane, mis0, nwin), (t_lo + 1) * 64 + lane, nwin, ntok);
-  WinR1 r1 = win_r1<FUSED>(a, (t_lo + 2) * 64 + lane, mis0, nwin);
+  const uint32_t per = (ntiles + gridDim.x - 1) / gridDim.x;
+  const uint32_t g_lo = min(ntiles, blockIdx.x * per), g_hi = min(ntiles, g_lo + per);
+  bool more = true;
+  auto take = [&]() -> uint32_t {  // the wave's next tile (wave-uniform), kNone at the end
+    if (!more) return kNone;
+    uint32_t k = 0;
+    if (lane == 0) k = atomicAdd(ctr, 1u);
+    const uint32_t t = g_lo + (uint32_t)__builtin_amdgcn_readfirstlane(__shfl((int)k, 0));
+    if (t >= g_hi) {
+      more = false;
+      return kNone;
+    }
+    return t;
+  };
+  uint32_t id0 = take(), id1 = take(), id2 = take();
+  if (id0 == kNone) return;  // wave-uniform, and no workgroup barrier follows
+  auto win_of = [&](uint32_t t) { return t == kNone ? nwin : t * 64 + lane; };
+  auto after = [&](uint32_t t) { return t == kNone ? nwin : min(nwin, (t + 1) * 64); };  // uniform
+  auto meta_of = [&](uint32_t i) { return win_meta(a, win_r1<FUSED>(a, i, mis0, nwin), i, nwin, ntok); };
+  WinMeta cur = meta_of(win_of(id0)), cx = meta_of(after(id0));
+  WinMeta nxt = meta_of(win_of(id1)), nx = meta_of(after(id1));
+  WinR1 r1 = win_r1<FUSED>(a, win_of(id2), mis0, nwin), r1x = win_r1<FUSED>(a, after(id2), mis0, nwin);
   auto wpos = [&](uint32_t t) { return (int64_t)t * 64 * kWin + (int64_t)lane * kWin - mis0; };
   auto is_edge = [&](uint32_t t) { return t == 0 || t + 1 == ntiles; };
-  Win64 dat = is_edge(t_lo) ? win_load<true>(a.in, wpos(t_lo), a.n) : win_load<false>(a.in, wpos(t_lo), a.n);
-  for (uint32_t tile = t_lo; tile < t_hi; ++tile) {
-    const uint32_t i = tile * 64 + lane;
+  Win64 dat = is_edge(id0) ? win_load<true>(a.in, wpos(id0), a.n) : win_load<false>(a.in, wpos(id0), a.n);
+  while (id0 != kNone) {
+    const uint32_t i = id0 * 64 + lane;
     Win64 ndat = dat;
-    if (tile + 1 < t_hi)
-      ndat = is_edge(tile + 1) ? win_load<true>(a.in, wpos(tile + 1), a.n) : win_load<false>(a.in, wpos(tile + 1), a.n);
+    if (id1 != kNone)
+      ndat = is_edge(id1) ? win_load<true>(a.in, wpos(id1), a.n) : win_load<false>(a.in, wpos(id1), a.n);
     // the state of the tile after next, and the first-round loads of the one after that:
     // issued here, they complete while this tile walks
-    const WinMeta n2 = win_meta(a, r1, (tile + 2) * 64 + lane, nwin, ntok);
-    r1 = win_r1<FUSED>(a, (tile + 3) * 64 + lane, mis0, nwin);
+    const WinMeta n2 = win_meta(a, r1, win_of(id2), nwin, ntok), n2x = win_meta(a, r1x, after(id2), nwin, ntok);
+    const uint32_t id3 = take();
+    r1 = win_r1<FUSED>(a, win_of(id3), mis0, nwin);
+    r1x = win_r1<FUSED>(a, after(id3), mis0, nwin);
     // this window's range of output slots ends where the next window's begins
     // (every shuffle runs with the whole wave active: a lane reading from an inactive
     // lane gets no defined value)
-    const uint32_t o_first = __shfl(cur.out, 0), o_next = __shfl(nxt.out, 0);
+    const uint32_t o_first = __shfl(cur.out, 0), o_next = cx.out;
     const uint32_t down = __shfl_down(cur.out, 1), fdown = __shfl_down(cur.fresh, 1);
-    const uint32_t f_next = __shfl(nxt.fresh, 0);
+    const uint32_t f_next = cx.fresh;
     const uint32_t P = __shfl(cur.tok, 0);  // start of the token in progress at the tile's start
-    const uint32_t span_end = (uint32_t)min<int64_t>((int64_t)(tile + 1) * 64 * kWin - mis0, a.n);
-    win_tile<DISC>(tb, a, stage, lane, cur, i, i < nwin, is_edge(tile), dat, wpos(tile), nwin, o_first, o_next,
+    const uint32_t span_end = (uint32_t)min<int64_t>((int64_t)(id0 + 1) * 64 * kWin - mis0, a.n);
+    win_tile<DISC>(tb, a, stage, lane, cur, i, i < nwin, is_edge(id0), dat, wpos(id0), nwin, o_first, o_next,
                    true, lane < 63 ? down : o_next, lane < 63 ? fdown : f_next, P, span_end, ntok);
     cur = nxt;
+    cx = nx;
     nxt = n2;
+    nx = n2x;
     dat = ndat;
+    id0 = id1;
+    id1 = id2;
+    id2 = id3;
   }
 }
 
@@ -3218,14 +3255,13 @@ static inline void mark(hipEvent_t const *ev, int i, hipStream_t s) {
   if (ev && ev[i]) (void)hipEventRecord(ev[i], s);
 }
 
-// Workgroups of the windowed emit: enough to fill every CU as far as its LDS allows,
-// looping over the wave tiles.
-static uint32_t win_grid(int nrows, uint32_t ntiles) {
+// Workgroups of the windowed emit: 16 waves per CU in workgroups of `waves`, fewer for a
+// short input (about one tile per wave).
+static uint32_t win_grid(uint32_t waves, uint32_t ntiles) {
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  const uint32_t per_cu = std::min<uint32_t>(8, (uint32_t)(160 * 1024 / win_lds_bytes(nrows)));
-  const uint32_t want = (ntiles + kWinWaves - 1) / kWinWaves;
-  const uint32_t g = std::max<uint32_t>(1, std::min<uint32_t>(want, (uint32_t)cus * std::max<uint32_t>(per_cu, 1)));
+  const uint32_t want = (ntiles + waves - 1) / waves;
+  const uint32_t g = std::max<uint32_t>(1, std::min<uint32_t>(want, (uint32_t)cus * (16 / waves)));
   return g >= 8 ? g & ~7u : g;  // whole rounds of the 8 XCDs
 }
 
@@ -3250,11 +3286,11 @@ static hipError_t count_scan_emit(const DevTable &t, const WalkArgs &a0, const P
   if (e != hipSuccess) return e;
   mark(ev, 3, s);
   if (win) {
-    const uint32_t ntiles = (windows_max(p.n) + 63) / 64;
+    const uint32_t ntiles = (windows_max(p.n) + 63) / 64, w = win_waves(t.nrows);
     if (t.all_counted)
-      k_emit_win<FUSED, false><<<win_grid(t.nrows, ntiles), kWinWaves * 64, win_lds_bytes(t.nrows), s>>>(a);
+      k_emit_win<FUSED, false><<<win_grid(w, ntiles), w * 64, win_lds_bytes(t.nrows, w), s>>>(a);
     else
-      k_emit_win<FUSED, true><<<win_grid(t.nrows, ntiles), kWinWaves * 64, win_lds_bytes(t.nrows), s>>>(a);
+      k_emit_win<FUSED, true><<<win_grid(w, ntiles), w * 64, win_lds_bytes(t.nrows, w), s>>>(a);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     a.fallback_only = 1;  // halted scans and long slices
