@@ -899,7 +899,7 @@ struct WalkArgs {
   uint32_t block;         // lanes per count workgroup (lane_pre's groups)
   uint32_t block_shift;   // log2(block)
   FastDiv lane_div;       // division by lane_bytes
-  int fallback_only;      // lane emit: run only when the windowed emit cannot
+  int fallback_only;      // one pass: the lane emit runs only for the scans the one-pass kernel left
   uint64_t *chunk_st;     // one pass: look-back status per workgroup of lanes
   uint32_t *chunk_ctr;    // one pass: next workgroup of lanes to take
   // emit
@@ -1224,22 +1224,16 @@ __global__ void __launch_bounds__(1024) k_scan(uint64_t *__restrict__ blk_sum, c
   }
 }
 
+// The lane emit of lane j: its slice walked again from its certified start, its tokens
+// written from its first output slot through the thread's ring (column threadIdx.x of
+// `ring`, blockDim.x columns).  The scan's first halted lane also reports the halt offset.
 template <bool MONO, bool FUSED>
-__global__ void __launch_bounds__(1024) k_emit(WalkArgs a) {
-  const uint32_t first = a.meta[0];
-  // beside the windowed emit, this kernel takes the scans that one cannot
-  if (a.fallback_only && first == kNone && a.meta[1] == 0) return;
-  const uint32_t j0 = blockIdx.x * blockDim.x;
-  if (j0 > first) return;  // the whole block lies after the first halted lane
-  const Lds l = carve_lds(a.nrows);
-  stage_tables(a, l, FUSED);
-  const Tables tb{lds_bytes_of(l.T), l.info, l.kind, a.sink, a.fail, 0};
-  const uint32_t j = j0 + threadIdx.x;
-  if (j >= a.nlanes || j > first) return;
-  const uint64_t off = a.blk_sum[blockIdx.x] + a.lane_pre[j];
+__device__ __forceinline__ void emit_lane(const WalkArgs &a, const Tables &tb, uint8_t *ring, uint32_t j,
+                                          uint32_t first) {
+  const uint64_t off = a.blk_sum[j >> a.block_shift] + a.lane_pre[j];
   const uint32_t s = a.cuts[j], e = FUSED ? a.ends[j] : a.cuts[j + 1];
   Ring r;
-  r.w = reinterpret_cast<uint32_t *>(l.ring) + threadIdx.x;
+  r.w = reinterpret_cast<uint32_t *>(ring) + threadIdx.x;
   r.stride = blockDim.x;
   r.kinds = a.kinds;
   r.lens = a.lens;
@@ -1255,6 +1249,22 @@ __global__ void __launch_bounds__(1024) k_emit(WalkArgs a) {
   else walk<true, MONO, false>(L, r, tb, a.in, a.n, s, e);
   ring_flush_tail(r);
   if (j == first) a.res->error_offset = L.tok;  // the halt offset: start of the failed token
+}
+
+// The lane emit of every lane up to the first halted one, a thread per lane.
+template <bool MONO, bool FUSED>
+__global__ void __launch_bounds__(1024) k_emit(WalkArgs a) {
+  const uint32_t first = a.meta[0];
+  // beside the one-pass kernel, this kernel takes the scans that one cannot
+  if (a.fallback_only && first == kNone && a.meta[1] == 0) return;
+  const uint32_t j0 = blockIdx.x * blockDim.x;
+  if (j0 > first) return;  // the whole block lies after the first halted lane
+  const Lds l = carve_lds(a.nrows);
+  stage_tables(a, l, FUSED);
+  const Tables tb{lds_bytes_of(l.T), l.info, l.kind, a.sink, a.fail, 0};
+  const uint32_t j = j0 + threadIdx.x;
+  if (j >= a.nlanes || j > first) return;
+  emit_lane<MONO, FUSED>(a, tb, l.ring, j, first);
 }
 
 
@@ -1284,10 +1294,15 @@ constexpr uint32_t kStageWords = 1280;   // staged words per wave
 __host__ __device__ inline size_t win_lds_bytes(int nrows, uint32_t waves = kWinWaves) {
   return lds_ring_offset(nrows) + (size_t)waves * kStageWords * 4;
 }
+// k_emit_win: a stage per wave, or a ring per thread when the scan takes the lane emit.
+__host__ __device__ inline size_t emit_win_lds_bytes(int nrows, uint32_t waves) {
+  const size_t stage = win_lds_bytes(nrows, waves), ring = lds_bytes(nrows, (int)waves * 64, true);
+  return stage > ring ? stage : ring;
+}
 // Waves of a windowed-emit workgroup: 16, 8 or 4, the most whose LDS fits in a CU.
 __host__ __device__ inline uint32_t win_waves(int nrows) {
   for (uint32_t w = 16; w > 4; w >>= 1)
-    if (win_lds_bytes(nrows, w) <= 160 * 1024) return w;
+    if (emit_win_lds_bytes(nrows, w) <= 160 * 1024) return w;
   return 4;
 }
 
@@ -1530,10 +1545,22 @@ __device__ __forceinline__ void win_tile(const Tables &tb, const WalkArgs &a, ui
 // the first window of the tile after it (in the input) begins; that window's start is
 // read for every tile, uniformly across the wave, since a wave's next tile is seldom the
 // adjacent one.
-template <bool FUSED, bool DISC>
+//
+// A scan with a halted slice, or a slice too long for the checkpoints, takes the lane emit
+// instead, in the same launch: each thread emits lanes j, j + the grid's threads, ... up
+// to the first halted lane.
+template <bool FUSED, bool DISC, bool MONO>
 __global__ void __launch_bounds__(1024) k_emit_win(WalkArgs a) {
-  if (a.meta[0] != kNone || a.meta[1] != 0 || a.res->status != 0 || a.n == 0) return;
+  const uint32_t first = a.meta[0];
   const Lds l = carve_lds(a.nrows);
+  if (first != kNone || a.meta[1] != 0) {  // uniform
+    stage_tables(a, l, false);
+    const Tables tb{lds_bytes_of(l.T), l.info, l.kind, a.sink, a.fail, 0};
+    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < a.nlanes && j <= first; j += gridDim.x * blockDim.x)
+      emit_lane<MONO, FUSED>(a, tb, l.ring, j, first);
+    return;
+  }
+  if (a.res->status != 0 || a.n == 0) return;
   uint32_t *ctr = l.red32;  // the workgroup's tile counter
   if (threadIdx.x == 0) *ctr = 0;
   stage_tables(a, l, false);  // its barrier publishes the zeroed counter
@@ -3181,7 +3208,7 @@ bool carve(void *ws, size_t ws_bytes, uint32_t n, uint32_t lane_bytes, uint32_t 
 }
 
 size_t walk_lds_bytes(int nrows, uint32_t block, bool emit) { return lds_bytes(nrows, (int)block, emit); }
-size_t window_lds_bytes(int nrows) { return win_lds_bytes(nrows); }
+size_t window_lds_bytes(int nrows) { return emit_win_lds_bytes(nrows, 4); }
 size_t onepass_lds_bytes(int nrows) { return one_lds_bytes(nrows); }
 
 static CertArg cert_arg(const CertMap &cm) {
@@ -3285,18 +3312,19 @@ static hipError_t count_scan_emit(const DevTable &t, const WalkArgs &a0, const P
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   mark(ev, 3, s);
-  if (win) {
+  if (win) {  // the windowed emit, or the lane emit in the same launch
     const uint32_t ntiles = (windows_max(p.n) + 63) / 64, w = win_waves(t.nrows);
-    if (t.all_counted)
-      k_emit_win<FUSED, false><<<win_grid(w, ntiles), w * 64, win_lds_bytes(t.nrows, w), s>>>(a);
-    else
-      k_emit_win<FUSED, true><<<win_grid(w, ntiles), w * 64, win_lds_bytes(t.nrows, w), s>>>(a);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    a.fallback_only = 1;  // halted scans and long slices
+    const uint32_t g = win_grid(w, ntiles);
+    const size_t lds = emit_win_lds_bytes(t.nrows, w);
+    if (t.all_counted && t.monotone) k_emit_win<FUSED, false, true><<<g, w * 64, lds, s>>>(a);
+    else if (t.all_counted) k_emit_win<FUSED, false, false><<<g, w * 64, lds, s>>>(a);
+    else if (t.monotone) k_emit_win<FUSED, true, true><<<g, w * 64, lds, s>>>(a);
+    else k_emit_win<FUSED, true, false><<<g, w * 64, lds, s>>>(a);
+  } else if (t.monotone) {
+    k_emit<true, FUSED><<<p.nblocks, p.block, smem_e, s>>>(a);
+  } else {
+    k_emit<false, FUSED><<<p.nblocks, p.block, smem_e, s>>>(a);
   }
-  if (t.monotone) k_emit<true, FUSED><<<p.nblocks, p.block, smem_e, s>>>(a);
-  else k_emit<false, FUSED><<<p.nblocks, p.block, smem_e, s>>>(a);
   e = hipGetLastError();
   mark(ev, 4, s);
   return e;
