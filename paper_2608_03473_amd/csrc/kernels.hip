@@ -1993,7 +1993,7 @@ __host__ __device__ inline size_t batch_lds_offset(int nrows, uint32_t ninst) {
 
 // The batch windowed emit: the combined table and a stage per wave.
 __host__ __device__ inline size_t batch_win_lds_bytes(int nrows, uint32_t ninst, uint32_t waves) {
-  return batch_lds_offset(nrows, ninst) + waves * (size_t)kStageWords * 4;
+  return batch_lds_offset(nrows, ninst) + waves * (size_t)kStageWords * 4 + 16;  // + the tile counter
 }
 // Waves of a windowed-emit workgroup: 16, 8 or 4, the most whose LDS fits; 0: none fits.
 __host__ __device__ inline uint32_t batch_win_waves(int nrows, uint32_t ninst) {
@@ -2969,20 +2969,36 @@ __device__ __forceinline__ WinMeta bwin_meta(const BatchArgs &a, const BDoc &c, 
   return m;
 }
 
-// Each wave takes a contiguous range of tiles (no queue: a device-scope atomic per tile
-// costs more than the tile) and walks it document segment by document segment; within a
-// segment the next tile's bytes and the following tiles' window states load while a tile
-// walks, as in the single-buffer windowed emit.
+// Each workgroup takes a contiguous range of tiles, and its waves claim runs of it through
+// a counter in LDS, guided: a run is a (2 × waves)-th of what remains, at least one tile,
+// so that runs are long at first and single tiles at the end, and the waves of a CU finish
+// together (a device-scope atomic per tile would cost more than the tile).  A wave walks a
+// run document segment by document segment; within a segment the next tile's bytes and
+// the following tiles' window states load while a tile walks, as in the single-buffer
+// windowed emit.
 __global__ void __launch_bounds__(1024) k_bemit_win(BatchArgs a) {
   if (a.meta[kNoWin] || a.total->status != 0) return;  // uniform: no barrier follows
-  const BatchLds l = batch_stage(a);
+  extern __shared__ __align__(16) uint8_t smem_w[];
   const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6, wpb = blockDim.x >> 6;
+  uint32_t *ctr = reinterpret_cast<uint32_t *>(smem_w + batch_win_lds_bytes(a.nrows, a.ninst, wpb) - 16);
+  if (threadIdx.x == 0) *ctr = 0;
+  const BatchLds l = batch_stage(a);  // its barrier publishes the zeroed counter
   uint32_t *stage = reinterpret_cast<uint32_t *>(l.ring) + wid * kStageWords;
   const uint32_t ntiles = a.meta[kNTiles];
   const uint32_t rm = refused_mask(a);
-  const uint32_t nwaves = gridDim.x * wpb, gw = blockIdx.x * wpb + wid;
-  const uint32_t per = (ntiles + nwaves - 1) / nwaves;
-  const uint32_t t_lo = min(ntiles, gw * per), t_hi = min(ntiles, t_lo + per);
+  const uint32_t per_g = (ntiles + gridDim.x - 1) / gridDim.x;
+  const uint32_t g_lo = min(ntiles, blockIdx.x * per_g), g_hi = min(ntiles, g_lo + per_g), span = g_hi - g_lo;
+  for (;;) {
+    uint32_t c0 = 0, len = 0;
+    if (lane == 0) {
+      const uint32_t done = *reinterpret_cast<volatile uint32_t *>(ctr);
+      len = max(1u, (span > done ? span - done : 0u) / (2 * wpb));
+      c0 = atomicAdd(ctr, len);
+    }
+    c0 = (uint32_t)__builtin_amdgcn_readfirstlane(__shfl((int)c0, 0));
+    len = (uint32_t)__builtin_amdgcn_readfirstlane(__shfl((int)len, 0));
+    if (c0 >= span) break;
+    const uint32_t t_lo = g_lo + c0, t_hi = g_lo + min(span, c0 + len);
   for (uint32_t t = t_lo; t < t_hi;) {
     const uint32_t d = a.tile_doc[t];
     const DocDev doc = a.docs[d];
@@ -3042,6 +3058,7 @@ __global__ void __launch_bounds__(1024) k_bemit_win(BatchArgs a) {
       nxt = n2;
       dat = ndat;
     }
+  }
   }
 }
 
