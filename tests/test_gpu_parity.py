@@ -100,6 +100,20 @@ def test_windowed_lane_starts_on_tile_boundaries(pad):
             check("clike_l", b, P.LEX_MODE_EXACT, opts(lane, path), pad_front=pad)
 
 
+@pytest.mark.parametrize("tiles", [1, 2, 15, 16, 17, 255, 257, 1025])
+def test_windowed_tile_counts(tiles):
+    """Tile counts around the windowed emit's split: workgroups take equal ranges of 64-window
+    tiles and their waves draw tiles one at a time from a counter in LDS, reading the first
+    window of the adjacent tile for each.  Counts below, at and above a workgroup's waves and
+    the number of workgroups, ragged (the last tile partial), at two buffer offsets."""
+    n = tiles * 4096 - 100
+    buf = workloads.clike(n, 700 + tiles)
+    for pad in (0, 37):
+        for path in (1, 2):
+            check("clike_l", buf, P.LEX_MODE_EXACT, opts(0, path), pad_front=pad, offsets=pad == 0)
+    check("clike_d", buf, P.LEX_MODE_DISCARD, opts(0, 2))
+
+
 def test_windowed_long_slice_falls_back():
     """A slice of 2^24 bytes or more (one 17 MiB comment): its checkpoints cannot hold its
     counts, so the lane emit takes the scan (after the one-pass kernel, its fallback)."""
