@@ -1053,7 +1053,12 @@ __global__ void __launch_bounds__(1024) k_count(WalkArgs a) {
     // every lane of the wave walks its lines together (walk_lines holds wave votes)
     CkSink ck{};
     if (CK) ck = ck_sink(a, j);
+    // the younger half of each SIMD's waves (slots 2 and 3 of 4) issue first: the SIMD's
+    // arbiter otherwise favours the older waves, and a CU's walk ends with its youngest
+    const uint32_t slot = __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 4) & 3;  // HW_ID wave slot
+    if (slot >= 2) __builtin_amdgcn_s_setprio(1);
     halted = walk_lines<CK>(L, r, tb, a.in, a.n, s, e, active, ck);
+    __builtin_amdgcn_s_setprio(0);
     // checkpoints hold the count in 24 bits: after a longer slice the windowed emit
     // stands down for the whole scan
     if (CK) big = active && e - s >= (1u << 24);
